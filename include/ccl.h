@@ -1,0 +1,136 @@
+/*
+ * ccl.h -- C ABI of the gfx950 (MI355X) two-pass connected component
+ * labeling library, after Gupta et al., "A New Parallel Algorithm for
+ * Two-Pass Connected Component Labeling" (arXiv 1606.05973).
+ *
+ * Problem (Section III): a binary image of H x W pixels; every object
+ * (foreground) pixel receives a label so that connected object pixels share a
+ * label.  Foreground here means a nonzero byte.  Connectivity is 8 (the only
+ * one the paper uses) or 4.
+ *
+ * Output numbering: 0 for background; the components are numbered 1..K in
+ * the order of their smallest raster index r*W + c (the first pixel of each
+ * component met in a row-major scan).  This is the numbering the paper's
+ * sequential CCLRemSP (Algorithm 1) produces; it does not depend on tiling
+ * or on scheduling, so results are bit-exact and reproducible.
+ *
+ * The work runs on a caller-provided HIP stream and is asynchronous: a call
+ * returns after launching; results are valid once the stream (or an event
+ * recorded after the call) has completed.  All pointers named "device" must
+ * be device memory of the current HIP device.
+ *
+ * Errors: argument errors are detected on the host before anything is
+ * launched and returned as a negative ccl_status; nothing is written then.
+ * CCL_ERR_HIP reports a failed HIP runtime call or launch.
+ */
+#ifndef CCL_H_
+#define CCL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hipStream_t;
+
+typedef enum {
+    CCL_OK = 0,
+    CCL_ERR_NULL = -1,      /* a required pointer is NULL                      */
+    CCL_ERR_SHAPE = -2,     /* H <= 0 or W <= 0                                 */
+    CCL_ERR_STRIDE = -3,    /* stride < W                                       */
+    CCL_ERR_CONN = -4,      /* conn is neither 4 nor 8                          */
+    CCL_ERR_TOO_LARGE = -5, /* H*W >= 2^31 - 1 (labels and raster keys are int32) */
+    CCL_ERR_NOMEM = -6,     /* the workspace could not be allocated             */
+    CCL_ERR_HIP = -7,       /* a HIP runtime call or kernel launch failed       */
+    CCL_ERR_TILE = -8,      /* unknown tile configuration id                    */
+    CCL_ERR_CAPTURE = -9,   /* workspace must grow while the stream is captured */
+    CCL_ERR_BATCH = -10     /* n < 0, or descs NULL with n > 0                  */
+} ccl_status;
+
+/*
+ * ccl_label -- label one image (the whole two-pass method of Section III/IV:
+ * tile-local scan with RemSP unions, parallel RemSP merge across tile
+ * boundaries, flatten, canonical ranking, labeling pass).
+ *
+ *   img     device, H rows of W bytes, row pitch `stride` bytes (>= W);
+ *           nonzero = foreground.  Read only.  Any alignment is accepted;
+ *           16-byte aligned rows take the fast load path.
+ *   H, W    image size in pixels, H*W < 2^31 - 1.
+ *   stride  row pitch of img in bytes.
+ *   conn    4 or 8.
+ *   labels  device, dense H x W int32, row pitch W elements.  Written
+ *           completely; also used as scratch during the call, so it must not
+ *           overlap img.  16-byte alignment and W % 4 == 0 take the fast
+ *           store path.
+ *   stream  HIP stream (NULL = default stream).
+ *
+ * Ownership: the caller owns img and labels.  The library owns a cached
+ * workspace per (device, stream), grown on demand (see ccl_reserve).
+ * Calls on different streams use different workspaces and may overlap;
+ * calls on one stream are serialised by the stream.
+ */
+int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
+              int32_t *labels, hipStream_t stream);
+
+/*
+ * ccl_label_ex -- as ccl_label, plus
+ *   num_components  device int32 receiving K, or NULL.
+ *   tile            tile configuration id from ccl_tile_config (0 = default).
+ */
+int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
+                 int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
+
+/* One image of a batch; fields as in ccl_label_ex. */
+typedef struct {
+    const uint8_t *img;      /* device */
+    int64_t H, W, stride;
+    int conn;                /* 4 or 8, may differ between images */
+    int32_t *labels;         /* device, dense H x W */
+    int32_t *num_components; /* device or NULL */
+} ccl_image_desc;
+
+/*
+ * ccl_label_batch -- label n independent images with one launch per phase
+ * for the whole batch (tiles of all images share each grid).
+ *   descs   host array of n descriptors (copied during the call).
+ *   n       number of images (0 is a no-op returning CCL_OK).
+ *   tile    tile configuration id used for every image (0 = default).
+ * Every descriptor is validated first; the first invalid one makes the call
+ * return its error with nothing launched.
+ */
+int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t stream);
+
+/* Workspace bytes one ccl_label_ex call needs for an H x W image with the
+ * given tile configuration (0 = default); 0 for invalid arguments.  Used for
+ * admission by HBM footprint: footprint = image + labels + workspace. */
+size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile);
+
+/* Workspace bytes for a batch call (descriptors as for ccl_label_batch). */
+size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile);
+
+/* Grow the workspace of (current device, stream) to at least `bytes` now,
+ * synchronising the stream if it has to reallocate.  Call it before
+ * capturing a stream into a HIP graph: inside capture the workspace cannot
+ * grow and a call that needs more returns CCL_ERR_CAPTURE. */
+int ccl_reserve(size_t bytes, hipStream_t stream);
+
+/* Free every cached workspace of the current device (synchronises the
+ * device first). */
+int ccl_release(void);
+
+/* Tile configuration `id` (1-based; 0 = default) -> tile height and width
+ * in pixels.  Returns CCL_OK, or CCL_ERR_TILE when id is out of range.
+ * ccl_tile_count() gives the number of configurations. */
+int ccl_tile_config(int id, int *tile_h, int *tile_w);
+int ccl_tile_count(void);
+
+/* Static description of a status code. */
+const char *ccl_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCL_H_ */

@@ -1,0 +1,189 @@
+"""Python binding of libccl.so (include/ccl.h): argument marshalling only.
+
+Every step of the labeling runs in the library's HIP kernels.  If the
+library is not built this module raises on import: there is no fallback.
+torch is used for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from .build import LIB
+
+if not os.path.exists(LIB):
+    raise ImportError(f"{LIB} is missing: build it with `python -m paper_1606_05973_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB)
+
+_u8p = ctypes.c_void_p
+_i32p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_stream = ctypes.c_void_p
+
+
+class ImageDesc(ctypes.Structure):
+    """ccl_image_desc of include/ccl.h."""
+    _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
+                ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p)]
+
+
+_lib.ccl_label.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _stream]
+_lib.ccl_label.restype = ctypes.c_int
+_lib.ccl_label_ex.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _i32p, ctypes.c_int, _stream]
+_lib.ccl_label_ex.restype = ctypes.c_int
+_lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int, _stream]
+_lib.ccl_label_batch.restype = ctypes.c_int
+_lib.ccl_workspace_bytes.argtypes = [_i64, _i64, ctypes.c_int, ctypes.c_int]
+_lib.ccl_workspace_bytes.restype = ctypes.c_size_t
+_lib.ccl_batch_workspace_bytes.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int]
+_lib.ccl_batch_workspace_bytes.restype = ctypes.c_size_t
+_lib.ccl_reserve.argtypes = [ctypes.c_size_t, _stream]
+_lib.ccl_reserve.restype = ctypes.c_int
+_lib.ccl_release.argtypes = []
+_lib.ccl_release.restype = ctypes.c_int
+_lib.ccl_tile_config.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.ccl_tile_config.restype = ctypes.c_int
+_lib.ccl_tile_count.argtypes = []
+_lib.ccl_tile_count.restype = ctypes.c_int
+_lib.ccl_strerror.argtypes = [ctypes.c_int]
+_lib.ccl_strerror.restype = ctypes.c_char_p
+
+CCL_OK = 0
+STATUS = {
+    "CCL_ERR_NULL": -1, "CCL_ERR_SHAPE": -2, "CCL_ERR_STRIDE": -3, "CCL_ERR_CONN": -4,
+    "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
+    "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10,
+}
+
+
+class CCLError(RuntimeError):
+    def __init__(self, status: int):
+        self.status = status
+        super().__init__(f"ccl status {status}: {strerror(status)}")
+
+
+def strerror(status: int) -> str:
+    return _lib.ccl_strerror(int(status)).decode()
+
+
+def _check(status: int):
+    if status != CCL_OK:
+        raise CCLError(status)
+
+
+def _stream_handle(stream) -> int | None:
+    """torch stream, raw hipStream_t as int (0 = default stream), or None for
+    torch's current stream."""
+    if isinstance(stream, int):
+        return stream or None
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _img_geometry(img: torch.Tensor):
+    if img.dim() != 2 or img.dtype != torch.uint8:
+        raise ValueError("image must be a 2-D uint8 tensor")
+    if not img.is_cuda:
+        raise ValueError("image must be on the GPU")
+    if img.stride(1) != 1:
+        raise ValueError("image rows must be contiguous (stride(1) == 1)")
+    H, W = img.shape
+    stride = img.stride(0) if H > 1 else W
+    return H, W, max(stride, W)
+
+
+def tile_configs():
+    """[(tile_h, tile_w)] for ids 1..n; id 0 means the default (id 1)."""
+    out = []
+    for i in range(1, _lib.ccl_tile_count() + 1):
+        h, w = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.ccl_tile_config(i, ctypes.byref(h), ctypes.byref(w)))
+        out.append((h.value, w.value))
+    return out
+
+
+def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
+          num_components: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Canonical int32 labels of a 2-D uint8 device image (nonzero = foreground)."""
+    H, W, stride = _img_geometry(img)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of the image's shape")
+    nc = 0
+    if num_components is not None:
+        if num_components.dtype != torch.int32 or num_components.numel() < 1 or not num_components.is_cuda:
+            raise ValueError("num_components must be a device int32 tensor")
+        nc = num_components.data_ptr()
+    st = _lib.ccl_label_ex(img.data_ptr(), H, W, stride, int(conn), out.data_ptr(), nc or None,
+                           int(tile), _stream_handle(stream))
+    _check(st)
+    return out
+
+
+def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: int, stream=None) -> int:
+    """Direct ccl_label call with raw device pointers; returns the status."""
+    return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
+
+
+def _descs(imgs, conns, outs, counts):
+    n = len(imgs)
+    arr = (ImageDesc * max(n, 1))()
+    for i, img in enumerate(imgs):
+        H, W, stride = _img_geometry(img)
+        arr[i].img = img.data_ptr()
+        arr[i].H, arr[i].W, arr[i].stride = H, W, stride
+        arr[i].conn = int(conns[i])
+        arr[i].labels = outs[i].data_ptr()
+        arr[i].num_components = counts[i].data_ptr() if counts is not None else None
+    return arr
+
+
+def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
+                stream=None):
+    """Label a list of images with one launch per phase for the whole batch.
+
+    conn: int or per-image list.  num_components: optional device int32
+    tensor with one slot per image."""
+    n = len(imgs)
+    conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
+    if outs is None:
+        outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
+    counts = None
+    if num_components is not None:
+        counts = [num_components[i:i + 1] for i in range(n)]
+    arr = _descs(imgs, conns, outs, counts)
+    _check(_lib.ccl_label_batch(arr, n, int(tile), _stream_handle(stream)))
+    return outs
+
+
+def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0) -> int:
+    return int(_lib.ccl_workspace_bytes(H, W, conn, tile))
+
+
+def batch_workspace_bytes(shapes, conn=8, tile: int = 0) -> int:
+    n = len(shapes)
+    arr = (ImageDesc * max(n, 1))()
+    for i, (H, W) in enumerate(shapes):
+        arr[i].img = 1
+        arr[i].labels = 1
+        arr[i].H, arr[i].W, arr[i].stride = H, W, W
+        arr[i].conn = conn if isinstance(conn, int) else conn[i]
+    return int(_lib.ccl_batch_workspace_bytes(arr, n, int(tile)))
+
+
+def reserve(nbytes: int, stream=None):
+    _check(_lib.ccl_reserve(int(nbytes), _stream_handle(stream)))
+
+
+def release():
+    _check(_lib.ccl_release())
+
+
+def library_path() -> str:
+    return LIB

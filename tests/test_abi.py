@@ -1,0 +1,96 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/ccl.h declares, and rejects bad arguments on the host with the
+documented status codes before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1606_05973_amd import build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccl.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ccl_[a-z_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_api():
+    names = _declared_functions()
+    for expected in ("ccl_label", "ccl_label_ex", "ccl_label_batch", "ccl_workspace_bytes",
+                     "ccl_batch_workspace_bytes", "ccl_reserve", "ccl_release", "ccl_tile_config",
+                     "ccl_tile_count", "ccl_strerror"):
+        assert expected in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(build.LIB), "libccl.so not built"
+    lib = ctypes.CDLL(build.LIB)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_codes_on_host():
+    from paper_1606_05973_amd import ccl
+    S = ccl.STATUS
+    dummy = 4096  # never dereferenced: the checks fail first
+    assert ccl.label_raw(0, 10, 10, 10, 8, dummy, stream=0) == S["CCL_ERR_NULL"]
+    assert ccl.label_raw(dummy, 10, 10, 10, 8, 0, stream=0) == S["CCL_ERR_NULL"]
+    assert ccl.label_raw(dummy, 0, 10, 10, 8, dummy, stream=0) == S["CCL_ERR_SHAPE"]
+    assert ccl.label_raw(dummy, 10, -1, 10, 8, dummy, stream=0) == S["CCL_ERR_SHAPE"]
+    assert ccl.label_raw(dummy, 10, 10, 9, 8, dummy, stream=0) == S["CCL_ERR_STRIDE"]
+    assert ccl.label_raw(dummy, 10, 10, 10, 6, dummy, stream=0) == S["CCL_ERR_CONN"]
+    assert ccl.label_raw(dummy, 1 << 16, 1 << 15, 1 << 15, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
+    lib = ccl._lib
+    assert lib.ccl_label_ex(dummy, 10, 10, 10, 8, dummy, None, 99, None) == S["CCL_ERR_TILE"]
+    assert lib.ccl_label_batch(None, -1, 0, None) == S["CCL_ERR_BATCH"]
+    assert lib.ccl_label_batch(None, 3, 0, None) == S["CCL_ERR_BATCH"]
+    assert lib.ccl_label_batch(None, 0, 0, None) == 0
+    # a bad descriptor anywhere in the batch rejects the whole call
+    arr = (ccl.ImageDesc * 2)()
+    for i in range(2):
+        arr[i].img, arr[i].labels = dummy, dummy
+        arr[i].H = arr[i].W = arr[i].stride = 8
+        arr[i].conn = 8
+    arr[1].conn = 5
+    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_CONN"]
+
+
+def test_strerror_and_tiles():
+    from paper_1606_05973_amd import ccl
+    for code in [0, *ccl.STATUS.values()]:
+        assert ccl.strerror(code) and ccl.strerror(code) != "unknown status"
+    assert ccl.strerror(12345) == "unknown status"
+    tiles = ccl.tile_configs()
+    assert tiles[0] == (32, 256) and len(tiles) == ccl._lib.ccl_tile_count()
+    for th, tw in tiles:
+        assert tw % 32 == 0 and th * tw <= 65536
+
+
+def test_workspace_bytes():
+    from paper_1606_05973_amd import ccl
+    assert ccl.workspace_bytes(0, 10) == 0
+    assert ccl.workspace_bytes(10, 10, conn=3) == 0
+    a = ccl.workspace_bytes(1000, 1000)
+    b = ccl.workspace_bytes(2000, 2000)
+    assert 0 < a < b
+    # edge buffers + boundary lists + segment counts: well under the labels' own size
+    assert ccl.workspace_bytes(21568, 21568) < 21568 * 21568
+    both = ccl.batch_workspace_bytes([(1000, 1000), (2000, 2000)])
+    assert both >= a + b - 1024
+
+
+def test_product_path_is_independent_of_the_oracle():
+    """The package and its sources neither import nor include the oracle."""
+    pkg = os.path.join(ROOT, "paper_1606_05973_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, flags=re.M), f
+                assert "ccl_oracle" not in text, f

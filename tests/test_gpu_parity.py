@@ -1,0 +1,176 @@
+"""Parity of the HIP library against the CPU oracle: bit-exact int32 labels
+and component counts on the same seeded bytes, called through the C ABI.
+
+Small and medium sizes span several tiles and ragged tails; the full-size
+workloads (21568^2, 16384^2, 20000^2) are compared element by element too,
+since the C oracle labels them in seconds."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1606_05973_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ccl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1606_05973_amd import ccl as mod
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(ccl, img_dev, conn, tile=0):
+    k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    lab = ccl.label(img_dev, conn=conn, tile=tile, num_components=k)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), int(k.item())
+
+
+def check(ccl, img_dev, conn, tile=0, what=""):
+    say(f"case {what} shape={tuple(img_dev.shape)} conn={conn} tile={tile}")
+    got, k = run(ccl, img_dev, conn, tile)
+    ref, kref = oracle.cclremsp(img_dev.cpu().numpy(), conn)
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        r, c = bad[0]
+        raise AssertionError(f"{what}: {len(bad)} pixels differ; first at {(r, c)} gpu={got[r, c]} "
+                             f"oracle={ref[r, c]}")
+    assert k == kref, (what, k, kref)
+    return got, k
+
+
+def test_config0_512_bernoulli(ccl):
+    img = inputs.bernoulli(512, 512, 0.5, seed=0, device=DEV)
+    check(ccl, img, 8, what="512x512 p=0.5 seed 0")
+
+
+SMALL = [(1, 1), (1, 300), (300, 1), (2, 2), (31, 255), (33, 257), (32, 256), (64, 512), (65, 513),
+         (100, 1000), (257, 1031), (999, 1000)]
+
+
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("conn", [8, 4])
+def test_random_shapes(ccl, shape, conn):
+    H, W = shape
+    for p in (0.1, 0.5, 0.9):
+        img = inputs.bernoulli(H, W, p, seed=H * 7 + W, device=DEV)
+        check(ccl, img, conn, what=f"bernoulli p={p}")
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_every_tile_shape(ccl, conn):
+    img = inputs.bernoulli(700, 900, 0.45, seed=3, device=DEV)
+    ref = None
+    for tile in range(0, len(ccl.tile_configs()) + 1):
+        got, _ = check(ccl, img, conn, tile=tile, what="tile sweep")
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("p", [0.3, 0.407, 0.593, 0.7])
+def test_percolation_and_grf(ccl, p):
+    img = inputs.bernoulli(1024, 1536, p, seed=11, device=DEV)
+    for conn in (8, 4):
+        check(ccl, img, conn, what=f"p={p}")
+    g = inputs.grf(777, 1111, sigma=2 + 10 * p, q=p, seed=5, device=DEV)
+    for conn in (8, 4):
+        check(ccl, g, conn, what=f"grf sigma={2 + 10 * p} q={p}")
+
+
+@pytest.mark.parametrize("name", inputs.ADVERSARIAL)
+def test_adversarial_medium(ccl, name):
+    img = inputs.adversarial(name, 1000, 1300, device=DEV)
+    for conn in (8, 4):
+        check(ccl, img, conn, what=name)
+
+
+def test_strided_unaligned_and_odd_width(ccl):
+    base = inputs.bernoulli(300, 1100, 0.5, seed=9, device=DEV)
+    view = base[:, 3:1000]  # 3-byte offset: unaligned rows, stride 1100, W = 997
+    for conn in (8, 4):
+        check(ccl, view, conn, what="unaligned view")
+    narrow = inputs.bernoulli(257, 37, 0.6, seed=2, device=DEV, stride=64)
+    for conn in (8, 4):
+        check(ccl, narrow, conn, what="stride 64, W 37")
+
+
+def test_nonzero_bytes_are_foreground(ccl):
+    g = torch.Generator().manual_seed(0)
+    vals = torch.randint(0, 256, (200, 333), generator=g, dtype=torch.int32)
+    vals[vals < 128] = 0
+    img = vals.to(torch.uint8).to(DEV)
+    for conn in (8, 4):
+        check(ccl, img, conn, what="byte values 0..255")
+
+
+def test_repeatable_and_out_buffer_reuse(ccl):
+    img = inputs.bernoulli(640, 480, 0.5, seed=21, device=DEV)
+    out = torch.full((640, 480), 12345, dtype=torch.int32, device=DEV)
+    a = ccl.label(img, 8, out=out).clone()
+    b = ccl.label(img, 8, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_batch_matches_single(ccl):
+    specs = inputs.batch_specs(24, seed=7, max_side=700)
+    imgs = [inputs.make(s, device=DEV) for s in specs]
+    conns = [8 if i % 3 else 4 for i in range(len(imgs))]
+    k = torch.full((len(imgs),), -1, dtype=torch.int32, device=DEV)
+    say(f"case batch n={len(imgs)}")
+    outs = ccl.label_batch(imgs, conn=conns, num_components=k)
+    torch.cuda.synchronize()
+    for i, img in enumerate(imgs):
+        ref, kref = oracle.cclremsp(img.cpu().numpy(), conns[i])
+        assert np.array_equal(outs[i].cpu().numpy(), ref), i
+        assert int(k[i].item()) == kref
+        single = ccl.label(img, conns[i])
+        assert torch.equal(single, outs[i])
+
+
+def test_empty_batch_and_single_pixel(ccl):
+    assert ccl.label_batch([]) == []
+    for v in (0, 1):
+        img = torch.full((1, 1), v, dtype=torch.uint8, device=DEV)
+        got, k = run(ccl, img, 8)
+        assert got[0, 0] == v and k == v
+
+
+# ---------------------------------------------------------------- full size
+def test_full_21568_bernoulli_8conn(ccl):
+    img = inputs.bernoulli(21568, 21568, 0.5, seed=0, device=DEV)
+    check(ccl, img, 8, what="21568^2 p=0.5")
+
+
+def test_full_21568_percolation_4conn(ccl):
+    img = inputs.bernoulli(21568, 21568, 0.593, seed=1, device=DEV)
+    check(ccl, img, 4, what="21568^2 p=0.593")
+
+
+def test_full_16384_grf(ccl):
+    img = inputs.grf(16384, 16384, 8.0, 0.5, seed=2, device=DEV)
+    check(ccl, img, 8, what="16384^2 grf sigma 8")
+
+
+@pytest.mark.parametrize("name", ["spiral", "checkerboard", "comb", "diagonal"])
+def test_full_20000_adversarial(ccl, name):
+    img = inputs.adversarial(name, 20000, 20000, device=DEV)
+    for conn in (8, 4):
+        got, k = check(ccl, img, conn, what=f"20000^2 {name}")
+        if name in ("spiral", "comb"):
+            assert k == 1
+        if name == "checkerboard":
+            assert k == (1 if conn == 8 else 20000 * 20000 // 2)
