@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the gfx950 two-pass connected component labeling.
+
+One step = one full ccl_label call (tile scan, boundary merge, flatten,
+rank scan, publish, labeling pass) on a device-resident image.  Default
+workload: the paper-scale single image, 21568 x 21568 uint8 (465.18 Mpx, the
+size of the paper's largest NLCD image at one byte per pixel), i.i.d.
+Bernoulli foreground p = 0.5 from seed 0, 8-connectivity.
+
+Prints ONE JSON line with the throughput (Gpixel/s), the roofline of the
+dominant kernel (its duration from HIP events recorded on the stream it runs
+on, during the timed steps), the CPU oracle timed on the host, and whether the
+benchmarked output is bit-exact against that oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E peak, GB/s
+BYTES_PER_PX = 5            # compulsory: 1 B image read + 4 B int32 label write
+# algorithmic bytes per pixel of each phase's launch
+PHASE_BYTES_PER_PX = {"tile_scan": 1.0, "labeling_pass": 5.0}
+METRIC = "Gpixel/s and % of HBM roofline, 8-conn, bit-exact; batched/served vs single"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_1606_05973_amd/csrc/ccl_kernels.hpp", "paper_1606_05973_amd/csrc/ccl_api.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload_key: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    ent = data.get("workloads", {}).get(workload_key, {}).get(kernel)
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=21568, help="image side (square)")
+    ap.add_argument("--p", type=float, default=0.5, help="Bernoulli foreground probability")
+    ap.add_argument("--conn", type=int, default=8)
+    ap.add_argument("--tile", type=int, default=0, help="tile configuration id (0 = default)")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-verify", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build labels on one GPU; --gpus must be 1 "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1606_05973_amd import ccl, inputs
+
+    dev = torch.device("cuda:0")
+    S = args.size
+    img = inputs.bernoulli(S, S, args.p, seed=0, device=dev)
+    out = torch.empty((S, S), dtype=torch.int32, device=dev)
+    kdev = torch.zeros(1, dtype=torch.int32, device=dev)
+    ccl.reserve(ccl.workspace_bytes(S, S, args.conn, args.tile))
+    th, tw = ccl.tile_shape(args.tile, args.conn)
+
+    for _ in range(args.warmup):
+        ccl.label(img, args.conn, out=out, tile=args.tile)
+    torch.cuda.synchronize()
+
+    ccl.profile(True)
+    ccl.profile_read()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kdev)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ccl.profile(False)
+    phases, ncalls = ccl.profile_read()
+    ms_step = start.elapsed_time(end) / args.steps
+    px = S * S
+    gpx = px / (ms_step * 1e-3) / 1e9
+    phase_ms = {k: v / max(ncalls, 1) for k, v in phases.items()}
+    dom = max(PHASE_BYTES_PER_PX, key=lambda k: phase_ms[k])
+    dom_ms = phase_ms[dom]
+    alg_bytes = PHASE_BYTES_PER_PX[dom] * px
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    workload_key = f"bernoulli{args.p}_{S}x{S}_conn{args.conn}_tile{th}x{tw}"
+    traffic = load_traffic(dom, workload_key)
+
+    record = {
+        "metric": METRIC,
+        "value": round(gpx, 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{S}x{S} uint8 Bernoulli p={args.p} seed 0, {args.conn}-connectivity, "
+                        "canonical int32 labels",
+            "H": S, "W": S, "conn": args.conn, "tile": [th, tw], "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "kernel_ms": round(dom_ms, 4),
+        },
+        "path_roofline_frac": round(BYTES_PER_PX * px / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
+        "wall_s_timed": round(wall, 4),
+        "num_components": int(kdev.item()),
+    }
+
+    if args.cpu_runs > 0 or not args.no_verify:
+        import numpy as np
+
+        import oracle
+        host = img.cpu().numpy()
+        times, ref = [], None
+        for _ in range(max(args.cpu_runs, 1)):
+            t = time.perf_counter()
+            ref, kref = oracle.cclremsp(host, args.conn)
+            times.append(time.perf_counter() - t)
+        if args.cpu_runs > 0:
+            med = statistics.median(times)
+            record["cpu_baseline"] = {
+                "value": round(px / med / 1e9, 4),
+                "unit": "Gpixel/s",
+                "cores": 1,
+                "kind": "oracle",
+                "sample": f"the full {S}x{S} image, single-threaded C CCLRemSP, median of {len(times)} runs "
+                          f"({med:.2f} s each)",
+            }
+        if not args.no_verify:
+            record["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), ref)) and int(kdev.item()) == kref
+
+    print(json.dumps(record), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,11 +120,27 @@ int ccl_reserve(size_t bytes, hipStream_t stream);
  * device first). */
 int ccl_release(void);
 
-/* Tile configuration `id` (1-based; 0 = default) -> tile height and width
- * in pixels.  Returns CCL_OK, or CCL_ERR_TILE when id is out of range.
- * ccl_tile_count() gives the number of configurations. */
-int ccl_tile_config(int id, int *tile_h, int *tile_w);
+/* Tile configuration `id` (1-based; 0 = default) -> block rows and tile
+ * width in pixels.  A tile is `block rows` x 2 image rows under
+ * 8-connectivity (the scan takes two rows at a time) and `block rows` x 1
+ * under 4-connectivity.  Returns CCL_OK, or CCL_ERR_TILE when id is out of
+ * range.  ccl_tile_count() gives the number of configurations. */
+int ccl_tile_config(int id, int *block_rows, int *tile_w);
 int ccl_tile_count(void);
+
+/*
+ * Phase timing.  ccl_profile(1) makes every later call record a HIP event on
+ * its stream before each of its CCL_NUM_PHASES kernels and after the last;
+ * ccl_profile_read waits for the recorded events and writes the summed
+ * milliseconds of each phase over all calls since the previous read into
+ * ms[0..nphase) (phases: tile scan, boundary merge, flatten, scan blocks,
+ * scan totals, publish, labeling pass), and the number of calls into
+ * *ncalls (may be NULL).  Used by the benchmark to time single kernels on
+ * the stream they run on.
+ */
+#define CCL_NUM_PHASES 7
+int ccl_profile(int enable);
+int ccl_profile_read(double *ms, int nphase, int *ncalls);
 
 /* Static description of a status code. */
 const char *ccl_strerror(int status);

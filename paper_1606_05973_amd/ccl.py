@@ -49,6 +49,10 @@ _lib.ccl_tile_config.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), cty
 _lib.ccl_tile_config.restype = ctypes.c_int
 _lib.ccl_tile_count.argtypes = []
 _lib.ccl_tile_count.restype = ctypes.c_int
+_lib.ccl_profile.argtypes = [ctypes.c_int]
+_lib.ccl_profile.restype = ctypes.c_int
+_lib.ccl_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.ccl_profile_read.restype = ctypes.c_int
 _lib.ccl_strerror.argtypes = [ctypes.c_int]
 _lib.ccl_strerror.restype = ctypes.c_char_p
 
@@ -98,7 +102,8 @@ def _img_geometry(img: torch.Tensor):
 
 
 def tile_configs():
-    """[(tile_h, tile_w)] for ids 1..n; id 0 means the default (id 1)."""
+    """[(block_rows, tile_w)] for ids 1..n; id 0 means the default (id 1).
+    Tile height is block_rows * 2 under 8-connectivity, block_rows under 4."""
     out = []
     for i in range(1, _lib.ccl_tile_count() + 1):
         h, w = ctypes.c_int(), ctypes.c_int()
@@ -162,6 +167,12 @@ def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Te
     return outs
 
 
+def tile_shape(tile: int, conn: int):
+    """(tile height, tile width) in pixels of configuration `tile` for `conn`."""
+    nsr, tw = tile_configs()[max(tile, 1) - 1]
+    return nsr * (2 if conn == 8 else 1), tw
+
+
 def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0) -> int:
     return int(_lib.ccl_workspace_bytes(H, W, conn, tile))
 
@@ -183,6 +194,22 @@ def reserve(nbytes: int, stream=None):
 
 def release():
     _check(_lib.ccl_release())
+
+
+PHASES = ("tile_scan", "boundary_merge", "flatten", "scan_blocks", "scan_totals", "publish", "labeling_pass")
+
+
+def profile(enable: bool):
+    """Record per-phase HIP events in every later call (see ccl_profile)."""
+    _check(_lib.ccl_profile(int(bool(enable))))
+
+
+def profile_read():
+    """({phase: summed ms}, number of calls) since the previous read."""
+    ms = (ctypes.c_double * len(PHASES))()
+    n = ctypes.c_int(0)
+    _check(_lib.ccl_profile_read(ms, len(PHASES), ctypes.byref(n)))
+    return {p: ms[i] for i, p in enumerate(PHASES)}, n.value
 
 
 def library_path() -> str:

@@ -15,46 +15,58 @@ namespace ccl {
 namespace {
 
 // ---------------------------------------------------------------- tiles
+// A tile configuration is (block rows, width).  The tile height is block
+// rows x 2 under 8-connectivity (two image rows per block row) and block
+// rows x 1 under 4-connectivity.  id 1 is the default.
 struct TileCfg {
-    int th, tw;
+    int nsr, tw;
 };
-// id 1 is the default.
-constexpr TileCfg kTiles[] = {{32, 256}, {64, 256}, {16, 512}, {64, 128}, {32, 128}, {16, 256}};
+constexpr TileCfg kTiles[] = {{32, 256}, {16, 256}, {16, 512}, {64, 128}, {32, 128}, {8, 512}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-inline int cap_of(const TileCfg &c) { return 2 * (c.th + c.tw); }
+inline int bh_of(int conn) { return conn == 8 ? 2 : 1; }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
-    int32_t NTY, NTX, NT, nblk, nedge;
-    size_t he, ve, bl_idx, bl_val, bl_cnt, seg, blk, bytes;
+    int32_t th, NTY, NTX, NT, nblk, nedge, nm, rcap, rw, cap;
+    size_t masks, rt, ck, cb, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
-Layout layout_of(int64_t H, int64_t W, const TileCfg &c) {
+Layout layout_of(int64_t H, int64_t W, int conn, const TileCfg &c) {
     Layout L{};
-    L.NTY = (int32_t)((H + c.th - 1) / c.th);
+    L.th = c.nsr * bh_of(conn);
+    L.NTY = (int32_t)((H + L.th - 1) / L.th);
     L.NTX = (int32_t)((W + c.tw - 1) / c.tw);
     L.NT = L.NTY * L.NTX;
-    int64_t nseg = H * (int64_t)L.NTX;
+    L.nm = L.th * (c.tw / 32);
+    L.rcap = c.nsr * (c.tw / 2);
+    L.rw = L.rcap / 32;
+    L.cap = 2 * (L.th + c.tw);
+    const int64_t nseg = H * (int64_t)L.NTX;
     L.nblk = (int32_t)((nseg + kScanChunk - 1) / kScanChunk);
-    L.nedge = (int32_t)((L.NTY - 1) * W + (L.NTX - 1) * H);
+    L.nedge = (int32_t)((L.NTY - 1) * ((W + 31) / 32) + (L.NTX - 1) * ((H + 31) / 32));
+    const size_t NT = (size_t)L.NT;
     size_t off = 0;
-    L.he = off;
-    off = align_up(off + (size_t)L.NTY * 2 * W * sizeof(uint16_t));
-    L.ve = off;
-    off = align_up(off + (size_t)L.NTX * 2 * H * sizeof(uint16_t));
-    L.bl_idx = off;
-    off = align_up(off + (size_t)L.NT * cap_of(c) * sizeof(int32_t));
-    L.bl_val = off;
-    off = align_up(off + (size_t)L.NT * cap_of(c) * sizeof(int32_t));
-    L.bl_cnt = off;
-    off = align_up(off + (size_t)L.NT * sizeof(int32_t));
-    L.seg = off;
-    off = align_up(off + (size_t)nseg * sizeof(int32_t));
-    L.blk = off;
-    off = align_up(off + (size_t)L.nblk * sizeof(int32_t));
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.masks = take(NT * L.nm * sizeof(uint32_t));
+    L.rt = take(NT * L.rcap * sizeof(uint16_t));
+    L.ck = take(NT * L.rcap * sizeof(uint16_t));
+    L.cb = take(NT * L.rw * sizeof(uint32_t));
+    L.tcnt = take(NT * 4 * sizeof(int32_t));
+    L.he = take((size_t)L.NTY * 2 * W * sizeof(uint16_t));
+    L.ve = take((size_t)L.NTX * 2 * H * sizeof(uint16_t));
+    L.uf = take(NT * L.cap * sizeof(uint64_t));
+    L.bval = take(NT * L.cap * sizeof(int32_t));
+    L.bkey = take(NT * L.cap * sizeof(uint16_t));
+    L.broot = take(NT * L.cap * sizeof(uint8_t));
+    L.seg = take((size_t)nseg * sizeof(int32_t));
+    L.blk = take((size_t)L.nblk * sizeof(int32_t));
     L.bytes = off;
     return L;
 }
@@ -128,11 +140,17 @@ Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     im.img = d.img;
     im.labels = d.labels;
     im.ncomp = d.num_components;
+    im.masks = reinterpret_cast<uint32_t *>(base + L.masks);
+    im.rt = reinterpret_cast<uint16_t *>(base + L.rt);
+    im.ck = reinterpret_cast<uint16_t *>(base + L.ck);
+    im.cb = reinterpret_cast<uint32_t *>(base + L.cb);
+    im.tcnt = reinterpret_cast<int32_t *>(base + L.tcnt);
     im.he = reinterpret_cast<uint16_t *>(base + L.he);
     im.ve = reinterpret_cast<uint16_t *>(base + L.ve);
-    im.bl_idx = reinterpret_cast<int32_t *>(base + L.bl_idx);
-    im.bl_val = reinterpret_cast<int32_t *>(base + L.bl_val);
-    im.bl_cnt = reinterpret_cast<int32_t *>(base + L.bl_cnt);
+    im.uf = reinterpret_cast<uint64_t *>(base + L.uf);
+    im.bval = reinterpret_cast<int32_t *>(base + L.bval);
+    im.bkey = reinterpret_cast<uint16_t *>(base + L.bkey);
+    im.broot = reinterpret_cast<uint8_t *>(base + L.broot);
     im.seg = reinterpret_cast<int32_t *>(base + L.seg);
     im.blk = reinterpret_cast<int32_t *>(base + L.blk);
     im.stride = d.stride;
@@ -145,59 +163,110 @@ Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     return im;
 }
 
-template <int TH, int TW>
+// ------------------------------------------------------------- profiling
+// When enabled, every call records one HIP event before each phase and one
+// after the last, on the call's own stream; ccl_profile_read turns them into
+// per-phase milliseconds.
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::vector<hipEvent_t>> g_prof_pending;  // one vector per call
+std::vector<hipEvent_t> g_prof_free;
+
+hipEvent_t prof_event() {
+    hipEvent_t e = nullptr;
+    if (!g_prof_free.empty()) {
+        e = g_prof_free.back();
+        g_prof_free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+struct PhaseMarks {
+    std::vector<hipEvent_t> ev;
+    hipStream_t s;
+    bool on;
+    explicit PhaseMarks(hipStream_t st) : s(st) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    void mark() {
+        if (!on)
+            return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        hipEvent_t e = prof_event();
+        if (e && hipEventRecord(e, s) == hipSuccess)
+            ev.push_back(e);
+        else
+            on = false;
+    }
+    ~PhaseMarks() {
+        if (!ev.empty()) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_prof_pending.push_back(ev);
+        }
+    }
+};
+
+template <int NSR, int TW, int BH>
 int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg, hipStream_t s) {
     if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
         return CCL_ERR_TOO_LARGE;
     const dim3 blk(kThreads);
-    hipLaunchKernelGGL((k_tile_scan<TH, TW>), dim3((uint32_t)tiles), blk, 0, s, b);
+    PhaseMarks pm(s);
+    pm.mark();
+    hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    pm.mark();
     if (edges > 0)
-        hipLaunchKernelGGL((k_merge<TH, TW>), dim3((uint32_t)((edges + kThreads - 1) / kThreads)), blk, 0, s, b);
-    hipLaunchKernelGGL((k_flatten<TH, TW>), dim3((uint32_t)tiles), blk, 0, s, b);
+        hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((edges + kThreads - 1) / kThreads)), blk, 0, s, b);
+    pm.mark();
+    hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    pm.mark();
     hipLaunchKernelGGL(k_scan_blocks, dim3((uint32_t)blocks), blk, 0, s, b);
+    pm.mark();
     hipLaunchKernelGGL(k_scan_top, dim3((uint32_t)nimg), blk, 0, s, b);
-    hipLaunchKernelGGL((k_publish<TH, TW>), dim3((uint32_t)tiles), blk, 0, s, b);
-    hipLaunchKernelGGL((k_relabel<TH, TW>), dim3((uint32_t)tiles), blk, 0, s, b);
+    pm.mark();
+    hipLaunchKernelGGL((k_publish<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    pm.mark();
+    hipLaunchKernelGGL((k_relabel<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
 
-int dispatch(const TileCfg &c, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
+int dispatch(const TileCfg &c, int bh, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
              hipStream_t s) {
-#define CCL_TILE_CASE(H_, W_) \
-    if (c.th == H_ && c.tw == W_) \
-        return launch_all<H_, W_>(b, tiles, edges, blocks, nimg, s);
+#define CCL_TILE_CASE(N_, W_)                                                   \
+    if (c.nsr == N_ && c.tw == W_)                                              \
+        return bh == 2 ? launch_all<N_, W_, 2>(b, tiles, edges, blocks, nimg, s) \
+                       : launch_all<N_, W_, 1>(b, tiles, edges, blocks, nimg, s);
     CCL_TILE_CASE(32, 256)
-    CCL_TILE_CASE(64, 256)
+    CCL_TILE_CASE(16, 256)
     CCL_TILE_CASE(16, 512)
     CCL_TILE_CASE(64, 128)
     CCL_TILE_CASE(32, 128)
-    CCL_TILE_CASE(16, 256)
+    CCL_TILE_CASE(8, 512)
 #undef CCL_TILE_CASE
     return CCL_ERR_TILE;
 }
 
-// Device table of a batch: kept per (device, stream) like the workspace.
-int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream) {
-    std::vector<Layout> lays(n);
-    size_t total = align_up((size_t)n * sizeof(Img));
-    for (int i = 0; i < n; i++) {
-        lays[i] = layout_of(descs[i].H, descs[i].W, c);
-        total += lays[i].bytes;
-    }
-    void *ws = nullptr;
-    int st = get_workspace(stream, total, &ws);
-    if (st != CCL_OK)
-        return st;
-    char *base = static_cast<char *>(ws);
+// Images of one connectivity share every launch; a batch mixing 4- and
+// 8-connectivity runs as two such groups, one after the other on the stream.
+// Workspace: [tables of both groups][per-image regions].
+int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+              const std::vector<size_t> &offs, char *base, Img *dtab, int bh, const TileCfg &c,
+              hipStream_t stream) {
+    const int n = (int)idx.size();
+    if (n == 0)
+        return CCL_OK;
     std::vector<Img> tab(n);
-    size_t off = align_up((size_t)n * sizeof(Img));
     int64_t tiles = 0, edges = 0, blocks = 0;
-    for (int i = 0; i < n; i++) {
-        tab[i] = make_img(descs[i], lays[i], base + off);
-        tab[i].tile0 = (int32_t)tiles;
-        tab[i].edge0 = (int32_t)edges;
-        tab[i].scan0 = (int32_t)blocks;
-        off += lays[i].bytes;
+    for (int k = 0; k < n; k++) {
+        const int i = idx[k];
+        tab[k] = make_img(descs[i], lays[i], base + offs[i]);
+        tab[k].tile0 = (int32_t)tiles;
+        tab[k].edge0 = (int32_t)edges;
+        tab[k].scan0 = (int32_t)blocks;
         tiles += lays[i].NT;
         edges += lays[i].nedge;
         blocks += lays[i].nblk;
@@ -210,11 +279,44 @@ int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t 
         b.one = tab[0];
         b.tab = nullptr;
     } else {
-        if (hipMemcpyAsync(base, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
+        if (hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
             return CCL_ERR_HIP;
-        b.tab = reinterpret_cast<const Img *>(base);
+        b.tab = dtab;
     }
-    return dispatch(c, b, tiles, edges, blocks, n, stream);
+    return dispatch(c, bh, b, tiles, edges, blocks, n, stream);
+}
+
+size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
+                   std::vector<size_t> *offs) {
+    size_t off = align_up((size_t)n * sizeof(Img));
+    for (int i = 0; i < n; i++) {
+        Layout L = layout_of(descs[i].H, descs[i].W, descs[i].conn, c);
+        if (lays)
+            lays->push_back(L);
+        if (offs)
+            offs->push_back(off);
+        off += L.bytes;
+    }
+    return off;
+}
+
+int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream) {
+    std::vector<Layout> lays;
+    std::vector<size_t> offs;
+    const size_t total = batch_bytes(descs, n, c, &lays, &offs);
+    void *ws = nullptr;
+    int st = get_workspace(stream, total, &ws);
+    if (st != CCL_OK)
+        return st;
+    char *base = static_cast<char *>(ws);
+    std::vector<int> g8, g4;
+    for (int i = 0; i < n; i++)
+        (descs[i].conn == 8 ? g8 : g4).push_back(i);
+    Img *dtab = reinterpret_cast<Img *>(base);
+    st = run_group(descs, g8, lays, offs, base, dtab, 2, c, stream);
+    if (st != CCL_OK)
+        return st;
+    return run_group(descs, g4, lays, offs, base, dtab + g8.size(), 1, c, stream);
 }
 
 }  // namespace
@@ -265,21 +367,21 @@ size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile) {
     int8_t dummy;
     if (check_image(&dummy, H, W, W, conn, &dummy) != CCL_OK)
         return 0;
-    return align_up(sizeof(Img)) + layout_of(H, W, c).bytes;
+    ccl_image_desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy),
+                     nullptr};
+    return batch_bytes(&d, 1, c, nullptr, nullptr);
 }
 
 size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile) {
     TileCfg c;
     if (resolve_tile(tile, &c) != CCL_OK || n < 0 || (n > 0 && !descs))
         return 0;
-    size_t total = align_up((size_t)n * sizeof(Img));
     for (int i = 0; i < n; i++) {
         int8_t dummy;
         if (check_image(&dummy, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, &dummy) != CCL_OK)
             return 0;
-        total += layout_of(descs[i].H, descs[i].W, c).bytes;
     }
-    return total;
+    return batch_bytes(descs, n, c, nullptr, nullptr);
 }
 
 int ccl_reserve(size_t bytes, hipStream_t stream) {
@@ -305,6 +407,46 @@ int ccl_release(void) {
     return CCL_OK;
 }
 
+int ccl_profile(int enable) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    return CCL_OK;
+}
+
+int ccl_profile_read(double *ms, int nphase, int *ncalls) {
+    if (!ms || nphase < 0)
+        return CCL_ERR_NULL;
+    std::vector<std::vector<hipEvent_t>> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        pend.swap(g_prof_pending);
+    }
+    for (int i = 0; i < nphase; i++)
+        ms[i] = 0.0;
+    int st = CCL_OK, calls = 0;
+    for (auto &ev : pend) {
+        if (hipEventSynchronize(ev.back()) != hipSuccess)
+            st = CCL_ERR_HIP;
+        for (size_t i = 0; i + 1 < ev.size() && (int)i < nphase; i++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess)
+                ms[i] += t;
+            else
+                st = CCL_ERR_HIP;
+        }
+        calls++;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (auto &ev : pend)
+            for (hipEvent_t e : ev)
+                g_prof_free.push_back(e);
+    }
+    if (ncalls)
+        *ncalls = calls;
+    return st;
+}
+
 int ccl_tile_count(void) { return kNumTiles; }
 
 int ccl_tile_config(int id, int *tile_h, int *tile_w) {
@@ -313,7 +455,7 @@ int ccl_tile_config(int id, int *tile_h, int *tile_w) {
     if (st != CCL_OK)
         return st;
     if (tile_h)
-        *tile_h = c.th;
+        *tile_h = c.nsr;
     if (tile_w)
         *tile_w = c.tw;
     return CCL_OK;

@@ -2,28 +2,31 @@
 //
 // Method (Gupta et al., arXiv 1606.05973, Sections III-IV), re-designed for
 // one MI355X:
-//   * the image is cut into TH x TW tiles; one workgroup labels one tile in
-//     LDS (the "local" phase of PARemSP, Algorithm 7, with 2-D tiles instead
-//     of row chunks);
-//   * inside a tile the scan works on horizontal runs held as 32-bit
-//     foreground masks (one mask word per lane); every pair of runs in
-//     consecutive rows that touch is united once with Rem's union with
-//     splicing (Algorithm 2) on an LDS parent array, concurrently, with the
-//     root link done by compare-and-swap as in the concurrent merger
-//     (Algorithm 8, locks replaced by CAS);
-//   * the union-find keys are local pixel indices of run starts; since every
-//     link points to a smaller index, every set's root is the set's first
-//     pixel in raster order;
-//   * across tiles, components meet at tile edges; the edge pixels' local
-//     roots are stored, and a second kernel unites them across every tile
-//     edge with the same CAS-based RemSP, on a parent array keyed by global
-//     raster index (the labels buffer itself, used sparsely);
-//   * flatten resolves every boundary root; components are ranked by their
-//     smallest raster index through counts per (image row, tile column)
-//     segment and a device exclusive scan;
-//   * the labeling pass (second pass) re-reads the image, rebuilds the tile
-//     labeling in LDS (deterministic: the local partition and its minima do
-//     not depend on scheduling) and writes every label once.
+//   * the image is cut into tiles; one workgroup scans one tile (the local
+//     phase of PARemSP, Algorithm 7, with 2-D tiles instead of row chunks);
+//   * the scan works on runs held as 32-bit foreground masks.  Under
+//     8-connectivity it takes two rows at a time, as ARemSP does with the
+//     mask of Fig. 1b: in a pair of rows every maximal stretch of columns
+//     holding a foreground pixel (a block run) is one connected set, so it is
+//     one union-find node.  Under 4-connectivity a node is a row run;
+//   * nodes are numbered in raster order of their start; every pair of
+//     nodes in consecutive block rows that touch is united once with Rem's
+//     union with splicing (Algorithm 2) on an LDS parent array, all lanes
+//     at once, the root link being a compare-and-swap as in the concurrent
+//     merger (Algorithm 8, locks replaced by CAS);
+//   * flatten (Algorithm 3's role) resolves every node; the tile then stores
+//     a node -> local component table, the canonical key of each local
+//     component (its first pixel in raster order), its foreground bitmask,
+//     the component of every tile-edge pixel, and per-row counts of the
+//     components that do not touch a shared tile edge;
+//   * a second kernel unites components across tile edges (Algorithm 7's
+//     boundary loop) with the same CAS-based RemSP on a compact global
+//     array whose entries pack (canonical key of parent, parent id), so the
+//     root of every set is its component's first raster pixel;
+//   * components are ranked by that pixel through counts per (image row,
+//     tile column) segment and a device exclusive scan;
+//   * the labeling pass (second pass) streams the tile's bitmask and tables
+//     and writes every int32 label once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,29 +34,35 @@
 
 namespace ccl {
 
-constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
-constexpr uint16_t kNone = 0xFFFFu;     // background in the edge buffers
-constexpr int kScanChunk = 4096;        // segment counts per scan block (256 x 16)
-constexpr int32_t kRootFlag = 1 << 30;  // boundary-list entry is a global root
-constexpr int32_t kLocalMask = 0xFFFF;  // boundary-list entry: local pixel index
+constexpr int kThreads = 256;       // threads per workgroup (4 wave64)
+constexpr uint16_t kNone = 0xFFFFu;  // background pixel in the edge buffers
+constexpr int kScanChunk = 4096;     // segment counts per scan block (256 x 16)
 
-// Per-image description used by every kernel.  Arrays live in the library
-// workspace except img / labels / ncomp, which belong to the caller.
+// Per-image description used by every kernel.  img / labels / ncomp belong
+// to the caller, the rest lives in the library workspace.  NT = NTY * NTX
+// tiles; RCAP, RW, CAP and NM are per-tile capacities fixed by the tile
+// shape (see Geo).
 struct Img {
     const uint8_t *img;   // H rows, pitch `stride` bytes
-    int32_t *labels;      // H x W, pitch W; also the global parent array
-    int32_t *ncomp;       // optional K output
-    uint16_t *he;         // [NTY][2][W]: local root of each pixel on the top(0)/bottom(1) tile rows
-    uint16_t *ve;         // [NTX][2][H]: same for the left(0)/right(1) tile columns
-    int32_t *bl_idx;      // [NT][CAP]: boundary local roots (local index | kRootFlag)
-    int32_t *bl_val;      // [NT][CAP]: interior roots before it in its row, then offset, then final label
-    int32_t *bl_cnt;      // [NT]
-    int32_t *seg;         // [H][NTX]: roots per (row, tile column) segment -> exclusive scan
-    int32_t *blk;         // [nblk]: scan block totals -> exclusive scan
+    int32_t *labels;      // H x W, pitch W
+    int32_t *ncomp;       // optional K output (device)
+    uint32_t *masks;      // [NT][NM]    foreground bitmask of each tile
+    uint16_t *rt;         // [NT][RCAP]  local component of each node
+    uint16_t *ck;         // [NT][RCAP]  canonical key (local pixel index) of each local component
+    uint32_t *cb;         // [NT][RW]    local component touches a shared tile edge (bit)
+    int32_t *tcnt;        // [NT][4]     nodes, components, boundary components
+    uint16_t *he;         // [NTY][2][W] boundary index of each top(0)/bottom(1) tile-row pixel
+    uint16_t *ve;         // [NTX][2][H] same for the left(0)/right(1) tile columns
+    uint64_t *uf;         // [NT][CAP]   global union-find: (key of parent << 32) | parent id
+    int32_t *bval;        // [NT][CAP]   interior roots before it in its row -> offset -> final label
+    uint16_t *bkey;       // [NT][CAP]   canonical key of boundary component j
+    uint8_t *broot;       // [NT][CAP]   boundary component j is its set's root
+    int32_t *seg;         // [H][NTX]    roots per (row, tile column) segment -> exclusive scan
+    int32_t *blk;         // [nblk]      scan block totals -> exclusive scan
     int64_t stride;
     int32_t H, W, NTY, NTX, conn;
     int32_t tile0;        // first tile of this image in a batch-wide tile numbering
-    int32_t edge0;        // first edge item (boundary merge kernel)
+    int32_t edge0;        // first edge segment (boundary merge kernel)
     int32_t scan0;        // first scan block
     int32_t nblk;
 };
@@ -86,34 +95,52 @@ __device__ __forceinline__ const Img &find_img(const Batch &b, int32_t item, int
 }
 
 // ------------------------------------------------------------------------
-// Relaxed atomics at a chosen scope (workgroup for LDS, agent for the
-// global parent array: the L2 caches of the eight XCDs are not coherent with
-// each other, so every access to a shared parent entry is an agent-scope
-// atomic).
+// Tile geometry.  NSR block rows of BH image rows (BH = 2 for 8-conn, 1 for
+// 4-conn), TW columns, NW mask words per row.
 // ------------------------------------------------------------------------
-template <int S>
-__device__ __forceinline__ int32_t aload(int32_t *p) {
+template <int NSR, int TW, int BH>
+struct Geo {
+    static constexpr int TH = NSR * BH;
+    static constexpr int NW = TW / 32;
+    static constexpr int NU = NSR * NW;                        // (block row, word) units
+    static constexpr int NM = TH * NW;                         // mask words
+    static constexpr int UPT = (NU + kThreads - 1) / kThreads;
+    static constexpr int MPT = (NM + kThreads - 1) / kThreads;
+    static constexpr int RCAP = NSR * (TW / 2);                // most nodes a tile can hold
+    static constexpr int RW = RCAP / 32;                       // words of a node/component bitmask
+    static constexpr int CAP = 2 * (TH + TW);                  // > pixels on the tile perimeter
+    static_assert(TW % 64 == 0, "tile width must be a multiple of 64");
+    static_assert(TH * TW <= 65535, "local pixel indices must fit 16 bits with one spare value");
+    static_assert(RCAP <= 65535, "local component ordinals must fit 16 bits");
+};
+
+// ------------------------------------------------------------------------
+// Relaxed atomics at a chosen scope (workgroup for LDS, agent for the
+// global array: the L2 caches of the eight XCDs are not coherent with each
+// other, so every access to a shared parent entry is an agent-scope atomic).
+// ------------------------------------------------------------------------
+template <int S, class T>
+__device__ __forceinline__ T aload(T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, S);
 }
-template <int S>
-__device__ __forceinline__ void astore(int32_t *p, int32_t v) {
+template <int S, class T>
+__device__ __forceinline__ void astore(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
 }
 // Compare-and-swap; returns the value found at *p (== expect on success).
-template <int S>
-__device__ __forceinline__ int32_t acas(int32_t *p, int32_t expect, int32_t v) {
+template <int S, class T>
+__device__ __forceinline__ T acas(T *p, T expect, T v) {
     __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
     return expect;
 }
 
-// Rem's union with splicing (Algorithm 2), made safe for concurrent callers
-// as in Algorithm 8: the link of a root is a CAS that succeeds only if it is
-// still a root; splices are plain atomic stores.  Every store writes a value
-// smaller than the node's own index, so the forest stays acyclic and every
-// root is the smallest element of its set.  Each iteration either returns,
-// moves rx or ry to a strictly smaller index, or retries a link that another
-// caller's successful link made fail (with the value that CAS observed), so
-// the loop ends even if a plain load returned an older parent.
+// Rem's union with splicing (Algorithm 2), safe for concurrent callers as in
+// Algorithm 8: a root is linked by a CAS that succeeds only while it is
+// still a root; splices are atomic stores.  Every store writes a value
+// smaller than the node's own, so the forest stays acyclic and each root is
+// its set's smallest element.  Each iteration returns, moves rx or ry to a
+// strictly smaller node, or retries a link that another caller's successful
+// link made fail (with the value the CAS observed), so the loop ends.
 template <int S>
 __device__ void rem_union(int32_t *P, int32_t x, int32_t y) {
     int32_t rx = x, ry = y;
@@ -146,8 +173,43 @@ __device__ void rem_union(int32_t *P, int32_t x, int32_t y) {
     }
 }
 
-// Find with full path compression.  Only used after all unions are done,
-// so the root is fixed and the only value ever stored is that root.
+// The same on the global array of packed entries (key of parent << 32 |
+// parent id): comparing packed parents compares their keys, so the root of
+// every set is the node with the smallest key.
+__device__ void rem_union_global(uint64_t *P, uint32_t x, uint32_t y) {
+    constexpr int S = __HIP_MEMORY_SCOPE_AGENT;
+    uint32_t rx = x, ry = y;
+    uint64_t px = aload<S>(P + rx);
+    uint64_t py = aload<S>(P + ry);
+    while (px != py) {
+        if (px > py) {
+            if ((uint32_t)px == rx) {
+                uint64_t seen = acas<S>(P + rx, px, py);
+                if (seen == px)
+                    return;
+                px = seen;
+                continue;
+            }
+            astore<S>(P + rx, py);
+            rx = (uint32_t)px;
+            px = aload<S>(P + rx);
+        } else {
+            if ((uint32_t)py == ry) {
+                uint64_t seen = acas<S>(P + ry, py, px);
+                if (seen == py)
+                    return;
+                py = seen;
+                continue;
+            }
+            astore<S>(P + ry, px);
+            ry = (uint32_t)py;
+            py = aload<S>(P + ry);
+        }
+    }
+}
+
+// Find with full path compression, used only after all unions are done (the
+// root is fixed and the only value ever stored is the root's).
 template <int S>
 __device__ int32_t find_compress(int32_t *P, int32_t x) {
     int32_t r = x, p;
@@ -162,11 +224,41 @@ __device__ int32_t find_compress(int32_t *P, int32_t x) {
     return r;
 }
 
+__device__ uint32_t find_compress_global(uint64_t *P, uint32_t x) {
+    constexpr int S = __HIP_MEMORY_SCOPE_AGENT;
+    uint32_t r = x;
+    uint64_t v;
+    for (;;) {
+        v = aload<S>(P + r);
+        if ((uint32_t)v == r)
+            break;
+        r = (uint32_t)v;
+    }
+    uint32_t y = x;
+    while (y != r) {
+        uint64_t nv = aload<S>(P + y);
+        astore<S>(P + y, v);
+        y = (uint32_t)nv;
+    }
+    return r;
+}
+
 // ------------------------------------------------------------------------
-// Foreground masks.  Bit j of a word is pixel x0 + j (nonzero byte).
+// Bit helpers.  Bit j of a mask word is column 32*w + j.
 // ------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t mask_le(int b) { return 0xFFFFFFFFu >> (31 - b); }  // bits 0..b
+__device__ __forceinline__ uint32_t mask_lt(int b) { return (1u << b) - 1u; }          // bits 0..b-1
+__device__ __forceinline__ uint32_t mask_ge(int b) { return 0xFFFFFFFFu << b; }        // bits b..31
+
+__device__ __forceinline__ int popc_before(const uint32_t *row, int c) {
+    int w = c >> 5, n = 0;
+    for (int k = 0; k < w; k++)
+        n += __popc(row[k]);
+    return n + __popc(row[w] & mask_lt(c & 31));
+}
 
 // 4 bytes -> 4 bits (byte != 0).  The add sets bit 7 of every byte whose
 // low 7 bits are nonzero (no carry crosses a byte); OR-ing the byte covers
@@ -197,433 +289,8 @@ __device__ __forceinline__ uint32_t load_word(const Img &im, int y, int x) {
     return m;
 }
 
-// ------------------------------------------------------------------------
-// Tile geometry and the LDS state of one tile.
-// ------------------------------------------------------------------------
-template <int TH, int TW>
-struct Geo {
-    static constexpr int NW = TW / 32;            // mask words per tile row
-    static constexpr int NU = TH * NW;            // (row, word) units
-    static constexpr int UPT = (NU + kThreads - 1) / kThreads;
-    static constexpr int NPX = TH * TW;
-    static constexpr int CAP = 2 * (TH + TW);     // > pixels on the tile perimeter
-    static_assert(TW % 32 == 0, "tile width must be a multiple of 32");
-    static_assert(NPX <= 65536, "local pixel indices must fit 16 bits");
-};
-
-template <int TH, int TW>
-struct TileLds {
-    using G = Geo<TH, TW>;
-    uint32_t M[G::NU];    // foreground masks
-    uint32_t S[G::NU];    // run-start masks
-    int32_t IN[G::NU];    // start of the run covering bit 0 when it continues from the left
-    uint32_t A[G::NU];    // flag bitmask (boundary roots in the scan; all roots in the relabel)
-    uint32_t B[G::NU];    // flag bitmask (interior roots)
-    int32_t P[G::NPX];    // parent array over local pixel indices (used at run starts)
-    int32_t rowv[TH];
-    int32_t list[G::CAP];
-    int32_t nlist;
-};
-
-// Start (local pixel index) of the run containing foreground pixel (r, c).
-template <int TH, int TW>
-__device__ __forceinline__ int32_t run_start(const TileLds<TH, TW> &t, int r, int c) {
-    constexpr int NW = Geo<TH, TW>::NW;
-    int w = c >> 5, b = c & 31;
-    uint32_t s = t.S[r * NW + w] & (0xFFFFFFFFu >> (31 - b));
-    return s ? (r * TW + (w << 5) + 31 - __clz(s)) : t.IN[r * NW + w];
-}
-
-// Tile-local labeling: after it returns (behind a barrier) P[s] is the local
-// root of run start s, and the local root is the component's first pixel in
-// raster order inside the tile.
-template <int TH, int TW>
-__device__ void tile_label(TileLds<TH, TW> &t, const Img &im, int y0, int x0) {
-    using G = Geo<TH, TW>;
-    constexpr int NW = G::NW;
-    const int tid = threadIdx.x;
-    const bool conn8 = im.conn == 8;
-
-    // load the tile as 32-bit foreground masks, clear the flag masks
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            t.M[u] = load_word(im, y0 + r, x0 + (w << 5));
-            t.A[u] = 0u;
-            t.B[u] = 0u;
-        }
-    }
-    if (tid == 0)
-        t.nlist = 0;
-    for (int r = tid; r < TH; r += kThreads)
-        t.rowv[r] = 0;
-    __syncthreads();
-
-    // run starts: foreground with background (or the tile edge) on the left
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int w = u % NW;
-            uint32_t m = t.M[u];
-            uint32_t mL = w ? t.M[u - 1] : 0u;
-            t.S[u] = m & ~((m << 1) | (mL >> 31));
-        }
-    }
-    __syncthreads();
-
-    // run continuing into the word, and one parent entry per run start
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t m = t.M[u], st = t.S[u];
-            int32_t in = -1;
-            if ((m & 1u) && !(st & 1u)) {
-                // every word between the run start and this one is all ones
-                int kk = w - 1;
-                while (kk > 0 && t.S[r * NW + kk] == 0u)
-                    kk--;
-                in = r * TW + (kk << 5) + 31 - __clz(t.S[r * NW + kk]);
-            }
-            t.IN[u] = in;
-            uint32_t bits = st;
-            while (bits) {
-                int b = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                int32_t s = r * TW + (w << 5) + b;
-                t.P[s] = s;
-            }
-        }
-    }
-    __syncthreads();
-
-    // unions between runs of row r and row r-1 that touch; each touching pair
-    // is united exactly once:
-    //   U1: first column of the overlap of the two runs,
-    //   U2: (8-conn) the upper run starts right after the lower run ends,
-    //   U3: (8-conn) the lower run starts right after the upper run ends.
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            if (r == 0)
-                continue;
-            const int base = w << 5;
-            uint32_t m = t.M[u];
-            uint32_t mL = w ? t.M[u - 1] : 0u;
-            uint32_t up = t.M[u - NW];
-            uint32_t uL = w ? t.M[u - NW - 1] : 0u;
-            uint32_t o = m & up;
-            uint32_t u1 = o & ~((o << 1) | ((mL & uL) >> 31));
-            while (u1) {
-                int b = __ffs(u1) - 1;
-                u1 &= u1 - 1u;
-                rem_union<__HIP_MEMORY_SCOPE_WORKGROUP>(t.P, run_start(t, r, base + b),
-                                                        run_start(t, r - 1, base + b));
-            }
-            if (conn8) {
-                uint32_t mR = (w < NW - 1) ? t.M[u + 1] : 0u;
-                uint32_t uR = (w < NW - 1) ? t.M[u - NW + 1] : 0u;
-                uint32_t mn = (m >> 1) | (mR << 31);   // pixel c+1, same row
-                uint32_t un = (up >> 1) | (uR << 31);  // pixel c+1, row above
-                uint32_t mp = (m << 1) | (mL >> 31);   // pixel c-1, same row
-                uint32_t upp = (up << 1) | (uL >> 31); // pixel c-1, row above
-                uint32_t u2 = m & ~mn & ~up & un;
-                uint32_t u3 = m & ~mp & ~up & upp;
-                while (u2) {
-                    int b = __ffs(u2) - 1;
-                    u2 &= u2 - 1u;
-                    rem_union<__HIP_MEMORY_SCOPE_WORKGROUP>(t.P, run_start(t, r, base + b),
-                                                            (r - 1) * TW + base + b + 1);
-                }
-                while (u3) {
-                    int b = __ffs(u3) - 1;
-                    u3 &= u3 - 1u;
-                    rem_union<__HIP_MEMORY_SCOPE_WORKGROUP>(t.P, r * TW + base + b,
-                                                            run_start(t, r - 1, base + b - 1));
-                }
-            }
-        }
-    }
-    __syncthreads();
-
-    // flatten: every run start points straight at its root
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t bits = t.S[u];
-            while (bits) {
-                int b = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                find_compress<__HIP_MEMORY_SCOPE_WORKGROUP>(t.P, r * TW + (w << 5) + b);
-            }
-        }
-    }
-    __syncthreads();
-}
-
-template <int TH, int TW>
-__device__ __forceinline__ int32_t gidx(const Img &im, int ty, int tx, int32_t li) {
-    return (ty * TH + li / TW) * im.W + tx * TW + li % TW;
-}
-
-__device__ __forceinline__ int popc_before(const uint32_t *row, int c) {
-    int w = c >> 5, b = c & 31, n = 0;
-    for (int k = 0; k < w; k++)
-        n += __popc(row[k]);
-    return n + __popc(row[w] & ((1u << b) - 1u));
-}
-
-// ------------------------------------------------------------------------
-// K1: tile scan.  Local labeling, then the tile's exports:
-//   edge buffers (local root per edge pixel, for the boundary merge),
-//   boundary roots (components touching an edge that has a neighbour tile)
-//     with the count of interior roots before them in their row,
-//   interior root counts per row segment,
-//   labels[g] = g for every boundary root g (global parent array).
-// ------------------------------------------------------------------------
-template <int TH, int TW>
-__global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
-    using G = Geo<TH, TW>;
-    constexpr int NW = G::NW;
-    __shared__ TileLds<TH, TW> t;
-    const Img &im = find_img(b, blockIdx.x, kTile);
-    const int ti = blockIdx.x - im.tile0;
-    const int ty = ti / im.NTX, tx = ti % im.NTX;
-    const int y0 = ty * TH, x0 = tx * TW;
-    const int tid = threadIdx.x;
-    tile_label<TH, TW>(t, im, y0, x0);
-
-    const bool top = ty > 0, bot = ty < im.NTY - 1, left = tx > 0, right = tx < im.NTX - 1;
-    // mark components that touch an edge shared with another tile
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t m = t.M[u];
-            if ((r == 0 && top) || (r == TH - 1 && bot)) {
-                uint32_t bits = t.S[u];
-                while (bits) {
-                    int bb = __ffs(bits) - 1;
-                    bits &= bits - 1u;
-                    int32_t root = t.P[r * TW + (w << 5) + bb];
-                    atomicOr(&t.A[root >> 5], 1u << (root & 31));
-                }
-            }
-            if (w == 0 && left && (m & 1u)) {
-                int32_t root = t.P[r * TW];
-                atomicOr(&t.A[root >> 5], 1u << (root & 31));
-            }
-            if (w == NW - 1 && right && (m >> 31)) {
-                int32_t root = t.P[run_start(t, r, TW - 1)];
-                atomicOr(&t.A[root >> 5], 1u << (root & 31));
-            }
-        }
-    }
-    // edge buffers
-    if (top || bot) {
-        for (int c = tid; c < 2 * TW; c += kThreads) {
-            int side = c / TW, cc = c % TW;
-            if ((side == 0 && !top) || (side == 1 && !bot))
-                continue;
-            int x = x0 + cc;
-            if (x >= im.W)
-                continue;
-            int r = side ? TH - 1 : 0;
-            uint16_t v = kNone;
-            if ((t.M[r * NW + (cc >> 5)] >> (cc & 31)) & 1u)
-                v = (uint16_t)t.P[run_start(t, r, cc)];
-            im.he[((int64_t)ty * 2 + side) * im.W + x] = v;
-        }
-    }
-    if (left || right) {
-        for (int q = tid; q < 2 * TH; q += kThreads) {
-            int side = q / TH, r = q % TH;
-            if ((side == 0 && !left) || (side == 1 && !right))
-                continue;
-            int y = y0 + r;
-            if (y >= im.H)
-                continue;
-            uint16_t v = kNone;
-            if (side == 0) {
-                if (t.M[r * NW] & 1u)
-                    v = (uint16_t)t.P[r * TW];
-            } else {
-                if (t.M[r * NW + NW - 1] >> 31)
-                    v = (uint16_t)t.P[run_start(t, r, TW - 1)];
-            }
-            im.ve[((int64_t)tx * 2 + side) * im.H + y] = v;
-        }
-    }
-    __syncthreads();
-
-    // classify the tile's components (one per local root)
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t bits = t.S[u];
-            while (bits) {
-                int bb = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                int32_t s = r * TW + (w << 5) + bb;
-                if (t.P[s] != s)
-                    continue;
-                if ((t.A[u] >> bb) & 1u) {
-                    int j = atomicAdd(&t.nlist, 1);
-                    t.list[j] = s;
-                    int32_t g = gidx<TH, TW>(im, ty, tx, s);
-                    im.labels[g] = g;
-                } else {
-                    atomicOr(&t.B[u], 1u << bb);
-                    atomicAdd(&t.rowv[r], 1);
-                }
-            }
-        }
-    }
-    __syncthreads();
-
-    const int n = t.nlist;
-    int32_t *bidx = im.bl_idx + (int64_t)ti * G::CAP;
-    int32_t *bval = im.bl_val + (int64_t)ti * G::CAP;
-    for (int j = tid; j < n; j += kThreads) {
-        int32_t s = t.list[j];
-        int r = s / TW, c = s % TW;
-        bidx[j] = s;
-        bval[j] = popc_before(&t.B[r * NW], c);
-    }
-    for (int r = tid; r < TH; r += kThreads)
-        if (y0 + r < im.H)
-            im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.rowv[r];
-    if (tid == 0)
-        im.bl_cnt[ti] = n;
-}
-
-// ------------------------------------------------------------------------
-// K2: boundary merge (Algorithm 7's boundary loop, Algorithm 8's merger).
-// One item per pixel of every interior tile edge.  8-connectivity: unite
-// with the pixel straight across if it is foreground, else with the two
-// diagonal ones (a foreground pixel straight across already joins its
-// diagonal neighbours, through its own tile or the perpendicular edge).
-// ------------------------------------------------------------------------
-template <int TH, int TW>
-__global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
-    const int32_t item = blockIdx.x * kThreads + threadIdx.x;
-    const Img &im = find_img(b, item, kEdge);
-    int32_t e = item - im.edge0;
-    const int32_t nH = (im.NTY - 1) * im.W;
-    const int32_t nV = (im.NTX - 1) * im.H;
-    if (e < 0 || e >= nH + nV)
-        return;
-    int32_t *P = im.labels;
-    if (e < nH) {
-        const int ty = 1 + e / im.W, x = e % im.W;
-        const uint16_t *lo = im.he + ((int64_t)ty * 2 + 0) * im.W;       // first row of tile row ty
-        const uint16_t *hi = im.he + ((int64_t)(ty - 1) * 2 + 1) * im.W; // last row of tile row ty-1
-        uint16_t l = lo[x];
-        if (l == kNone)
-            return;
-        const int32_t ge = gidx<TH, TW>(im, ty, x / TW, l);
-        uint16_t h = hi[x];
-        if (h != kNone) {
-            if ((x % TW) != 0 && lo[x - 1] == l && hi[x - 1] == h)
-                return;  // same pair as the previous column
-            rem_union<__HIP_MEMORY_SCOPE_AGENT>(P, ge, gidx<TH, TW>(im, ty - 1, x / TW, h));
-        } else if (im.conn == 8) {
-            if (x > 0 && hi[x - 1] != kNone)
-                rem_union<__HIP_MEMORY_SCOPE_AGENT>(P, ge, gidx<TH, TW>(im, ty - 1, (x - 1) / TW, hi[x - 1]));
-            if (x + 1 < im.W && hi[x + 1] != kNone)
-                rem_union<__HIP_MEMORY_SCOPE_AGENT>(P, ge, gidx<TH, TW>(im, ty - 1, (x + 1) / TW, hi[x + 1]));
-        }
-    } else {
-        e -= nH;
-        const int tx = 1 + e / im.H, y = e % im.H;
-        const uint16_t *rc = im.ve + ((int64_t)tx * 2 + 0) * im.H;       // first column of tile column tx
-        const uint16_t *lc = im.ve + ((int64_t)(tx - 1) * 2 + 1) * im.H; // last column of tile column tx-1
-        uint16_t rv = rc[y];
-        if (rv == kNone)
-            return;
-        const int32_t ge = gidx<TH, TW>(im, y / TH, tx, rv);
-        uint16_t lv = lc[y];
-        if (lv != kNone) {
-            if ((y % TH) != 0 && rc[y - 1] == rv && lc[y - 1] == lv)
-                return;
-            rem_union<__HIP_MEMORY_SCOPE_AGENT>(P, ge, gidx<TH, TW>(im, y / TH, tx - 1, lv));
-        } else if (im.conn == 8) {
-            if (y > 0 && lc[y - 1] != kNone)
-                rem_union<__HIP_MEMORY_SCOPE_AGENT>(P, ge, gidx<TH, TW>(im, (y - 1) / TH, tx - 1, lc[y - 1]));
-            if (y + 1 < im.H && lc[y + 1] != kNone)
-                rem_union<__HIP_MEMORY_SCOPE_AGENT>(P, ge, gidx<TH, TW>(im, (y + 1) / TH, tx - 1, lc[y + 1]));
-        }
-    }
-}
-
-// ------------------------------------------------------------------------
-// K3a: flatten the boundary roots of one tile; a boundary root that is its
-// own global root is the first pixel of its component.  Adds those roots to
-// the segment counts and stores their offset inside their row segment.
-// ------------------------------------------------------------------------
-template <int TH, int TW>
-__global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
-    using G = Geo<TH, TW>;
-    constexpr int NW = G::NW;
-    __shared__ uint32_t R[G::NU];
-    __shared__ int32_t rowv[TH];
-    __shared__ uint8_t isr[G::CAP];
-    const Img &im = find_img(b, blockIdx.x, kTile);
-    const int ti = blockIdx.x - im.tile0;
-    const int n = im.bl_cnt[ti];
-    if (n == 0)
-        return;
-    const int ty = ti / im.NTX, tx = ti % im.NTX;
-    const int y0 = ty * TH;
-    const int tid = threadIdx.x;
-    for (int u = tid; u < G::NU; u += kThreads)
-        R[u] = 0u;
-    for (int r = tid; r < TH; r += kThreads)
-        rowv[r] = 0;
-    __syncthreads();
-    int32_t *bidx = im.bl_idx + (int64_t)ti * G::CAP;
-    int32_t *bval = im.bl_val + (int64_t)ti * G::CAP;
-    for (int j = tid; j < n; j += kThreads) {
-        int32_t s = bidx[j] & kLocalMask;
-        int32_t g = gidx<TH, TW>(im, ty, tx, s);
-        int32_t root = find_compress<__HIP_MEMORY_SCOPE_AGENT>(im.labels, g);
-        bool is = root == g;
-        isr[j] = is;
-        if (is) {
-            atomicOr(&R[s >> 5], 1u << (s & 31));
-            atomicAdd(&rowv[s / TW], 1);
-        }
-    }
-    __syncthreads();
-    for (int j = tid; j < n; j += kThreads) {
-        if (isr[j]) {
-            int32_t s = bidx[j] & kLocalMask;
-            int r = s / TW, c = s % TW;
-            bval[j] += popc_before(&R[r * NW], c);
-            bidx[j] = s | kRootFlag;
-        }
-    }
-    for (int r = tid; r < TH; r += kThreads)
-        if (rowv[r] && y0 + r < im.H)
-            im.seg[(int64_t)(y0 + r) * im.NTX + tx] += rowv[r];
-}
-
-// ------------------------------------------------------------------------
-// K4a / K4b: exclusive scan of the segment counts in raster order.
-// K4a scans blocks of kScanChunk entries in place and stores block totals;
-// K4b (one workgroup per image) scans the block totals and stores K.
-// ------------------------------------------------------------------------
+// Exclusive prefix sum of v over the workgroup; *total gets the sum.
+// Contains two barriers; every thread must call it.
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
     __shared__ int32_t wsum[kThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -649,6 +316,499 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *tota
     return before + incl - v;
 }
 
+// Exclusive popcount prefix of n bitmask words (n may exceed kThreads).
+__device__ __forceinline__ int32_t popcount_prefix(const uint32_t *bits, int32_t *pref, int n) {
+    int32_t carry = 0;
+    for (int base = 0; base < n; base += kThreads) {
+        int i = base + threadIdx.x;
+        int32_t v = i < n ? __popc(bits[i]) : 0;
+        int32_t tot;
+        int32_t ex = block_exclusive_scan(v, &tot);
+        if (i < n)
+            pref[i] = carry + ex;
+        carry += tot;
+    }
+    return carry;
+}
+
+__device__ __forceinline__ int32_t rank_of(const uint32_t *bits, const int32_t *pref, int32_t k) {
+    return pref[k >> 5] + __popc(bits[k >> 5] & mask_lt(k & 31));
+}
+
+// ------------------------------------------------------------------------
+// Block runs of a tile: masks, starts and node ordinals.  Shared by the
+// scan and the labeling pass so both number the nodes identically.
+// ------------------------------------------------------------------------
+template <int NSR, int TW, int BH>
+struct RunLds {
+    using G = Geo<NSR, TW, BH>;
+    uint32_t M[G::NM];      // foreground masks, row-major
+    uint32_t S[G::NU];      // block-run starts per (block row, word)
+    int32_t base[G::NU];    // ordinal of the first node starting in the unit
+};
+
+template <int NSR, int TW, int BH>
+__device__ __forceinline__ uint32_t block_mask(const uint32_t *M, int R, int w) {
+    constexpr int NW = Geo<NSR, TW, BH>::NW;
+    uint32_t m = M[(R * BH) * NW + w];
+    if (BH == 2)
+        m |= M[(R * BH + 1) * NW + w];
+    return m;
+}
+
+// Node ordinal of the block run of block row R containing column c (which
+// must be foreground in that block row).
+template <int NSR, int TW, int BH>
+__device__ __forceinline__ int32_t node_at(const RunLds<NSR, TW, BH> &t, int R, int c) {
+    constexpr int NW = Geo<NSR, TW, BH>::NW;
+    const int u = R * NW + (c >> 5);
+    return t.base[u] - 1 + __popc(t.S[u] & mask_le(c & 31));
+}
+
+// Fills S and base from M; returns the number of nodes (same on all threads).
+template <int NSR, int TW, int BH>
+__device__ int32_t number_runs(RunLds<NSR, TW, BH> &t) {
+    using G = Geo<NSR, TW, BH>;
+    constexpr int NW = G::NW;
+    int32_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < G::UPT; k++) {
+        const int u = threadIdx.x + k * kThreads;
+        int32_t cnt = 0;
+        if (u < G::NU) {
+            const int R = u / NW, w = u % NW;
+            uint32_t bm = block_mask<NSR, TW, BH>(t.M, R, w);
+            uint32_t bl = w ? block_mask<NSR, TW, BH>(t.M, R, w - 1) : 0u;
+            uint32_t s = bm & ~((bm << 1) | (bl >> 31));
+            t.S[u] = s;
+            cnt = __popc(s);
+        }
+        int32_t tot;
+        int32_t ex = block_exclusive_scan(cnt, &tot);
+        if (u < G::NU)
+            t.base[u] = carry + ex;
+        carry += tot;
+    }
+    return carry;
+}
+
+// ------------------------------------------------------------------------
+// K1: tile scan.
+// ------------------------------------------------------------------------
+template <int NSR, int TW, int BH>
+struct ScanLds : RunLds<NSR, TW, BH> {
+    using G = Geo<NSR, TW, BH>;
+    int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
+    uint16_t RT[G::RCAP];   // component ordinal of each node
+    uint32_t RFB[G::RW];    // root nodes (bit per node)
+    int32_t RFP[G::RW];
+    uint32_t BFB[G::RW];    // boundary components (bit per component)
+    int32_t BFP[G::RW];
+    uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
+    int32_t rowcnt[G::TH];
+};
+
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
+    using G = Geo<NSR, TW, BH>;
+    constexpr int NW = G::NW, TH = G::TH;
+    constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
+    __shared__ ScanLds<NSR, TW, BH> t;
+    const Img &im = find_img(b, blockIdx.x, kTile);
+    const int ti = blockIdx.x - im.tile0;
+    const int ty = ti / im.NTX, tx = ti % im.NTX;
+    const int y0 = ty * TH, x0 = tx * TW;
+    const int tid = threadIdx.x;
+    const bool conn8 = BH == 2;
+
+    // 1. foreground masks (kept in LDS and stored for the labeling pass)
+    uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+#pragma unroll
+    for (int k = 0; k < G::MPT; k++) {
+        const int i = tid + k * kThreads;
+        if (i < G::NM) {
+            const int r = i / NW, w = i % NW;
+            uint32_t m = load_word(im, y0 + r, x0 + (w << 5));
+            t.M[i] = m;
+            gmask[i] = m;
+            t.RK[i] = 0u;
+        }
+    }
+    for (int r = tid; r < TH; r += kThreads)
+        t.rowcnt[r] = 0;
+    for (int i = tid; i < G::RW; i += kThreads) {
+        t.RFB[i] = 0u;
+        t.BFB[i] = 0u;
+    }
+    __syncthreads();
+
+    // 2. block runs and their ordinals
+    const int32_t n_runs = number_runs<NSR, TW, BH>(t);
+    for (int k = tid; k < n_runs; k += kThreads)
+        t.P[k] = k;
+    __syncthreads();
+
+    // 3. unite touching nodes of block rows R-1 and R.  The contact rows are
+    // the last row of R-1 (u) and the first row of R (m).  Each touching pair
+    // of row runs is met exactly once: U1 at the first column of their
+    // overlap, U2 (8-conn) where the upper run starts just right of the
+    // lower one's end, U3 (8-conn) where the lower run starts just right of
+    // the upper one's end.
+#pragma unroll
+    for (int k = 0; k < G::UPT; k++) {
+        const int u = tid + k * kThreads;
+        if (u >= G::NU)
+            continue;
+        const int R = u / NW, w = u % NW;
+        if (R == 0)
+            continue;
+        const int rm = R * BH, ru = R * BH - 1;
+        const uint32_t m = t.M[rm * NW + w];
+        const uint32_t mL = w ? t.M[rm * NW + w - 1] : 0u;
+        const uint32_t mR = (w < NW - 1) ? t.M[rm * NW + w + 1] : 0u;
+        const uint32_t up = t.M[ru * NW + w];
+        const uint32_t uL = w ? t.M[ru * NW + w - 1] : 0u;
+        const uint32_t uR = (w < NW - 1) ? t.M[ru * NW + w + 1] : 0u;
+        const uint32_t o = m & up;
+        const uint32_t u1 = o & ~((o << 1) | ((mL & uL) >> 31));
+        uint32_t u2 = 0u, u3 = 0u;
+        if (conn8) {
+            const uint32_t mn = (m >> 1) | (mR << 31);
+            const uint32_t un = (up >> 1) | (uR << 31);
+            const uint32_t mp = (m << 1) | (mL >> 31);
+            const uint32_t upp = (up << 1) | (uL >> 31);
+            u2 = m & ~mn & ~up & un;
+            u3 = m & ~mp & ~up & upp;
+        }
+        uint64_t cm = (uint64_t)(u1 | u3) | ((uint64_t)u2 << 32);
+        if (!cm)
+            continue;
+        const uint32_t sR = t.S[u];
+        const int32_t bR = t.base[u] - 1;
+        const int uu = u - NW;
+        const uint32_t sU = t.S[uu];
+        const int32_t bU = t.base[uu] - 1;
+        const uint32_t sUL = w ? t.S[uu - 1] : 0u;
+        const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
+        const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
+        const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
+        while (cm) {
+            const int bit = __ffsll((unsigned long long)cm) - 1;
+            cm &= cm - 1;
+            const int c = bit & 31;
+            const int d = (bit >> 5) ? 1 : (((u1 >> c) & 1u) ? 0 : -1);
+            const int32_t a = bR + __popc(sR & mask_le(c));
+            const int p = c + d;
+            const uint32_t sp = p < 0 ? sUL : (p > 31 ? sUR : sU);
+            const int32_t bp = p < 0 ? bUL : (p > 31 ? bUR : bU);
+            const int32_t bb = bp + __popc(sp & mask_le(p & 31));
+            rem_union<WG>(t.P, a, bb);
+        }
+    }
+    __syncthreads();
+
+    // 4. flatten; roots are numbered in node order (local components)
+    for (int k = tid; k < n_runs; k += kThreads)
+        if (find_compress<WG>(t.P, k) == k)
+            atomicOr(&t.RFB[k >> 5], 1u << (k & 31));
+    __syncthreads();
+    const int32_t n_comp = popcount_prefix(t.RFB, t.RFP, (n_runs + 31) >> 5);
+    __syncthreads();
+    for (int k = tid; k < n_runs; k += kThreads)
+        t.RT[k] = (uint16_t)rank_of(t.RFB, t.RFP, t.P[k]);
+    __syncthreads();
+
+    // 5. canonical key of each component: its first pixel in raster order,
+    // the minimum over its nodes of the node's first pixel (top row first)
+    for (int c = tid; c < n_comp; c += kThreads)
+        t.P[c] = 0x7FFFFFFF;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < G::UPT; k++) {
+        const int u = tid + k * kThreads;
+        if (u >= G::NU)
+            continue;
+        const int R = u / NW, w = u % NW;
+        uint32_t bits = t.S[u];
+        int32_t ord = t.base[u];
+        while (bits) {
+            const int bb = __ffs(bits) - 1;
+            bits &= bits - 1u;
+            int32_t key;
+            if (BH == 1) {
+                key = R * TW + (w << 5) + bb;
+            } else {
+                const int r0 = R * BH;
+                key = (r0 + 1) * TW + (w << 5) + bb;  // no top pixel: the run's start
+                int ww = w, from = bb;
+                for (;;) {
+                    const uint32_t tt = t.M[r0 * NW + ww] & mask_ge(from);
+                    const uint32_t gap = ~block_mask<NSR, TW, BH>(t.M, R, ww) & mask_ge(from);
+                    if (tt && (!gap || __ffs(tt) < __ffs(gap))) {
+                        key = r0 * TW + (ww << 5) + __ffs(tt) - 1;
+                        break;
+                    }
+                    if (gap || ww == NW - 1)
+                        break;
+                    ww++;
+                    from = 0;
+                }
+            }
+            atomicMin(&t.P[t.RT[ord]], key);
+            ord++;
+        }
+    }
+    __syncthreads();
+
+    // 6. components touching an edge shared with another tile
+    const bool top = ty > 0, bot = ty < im.NTY - 1, left = tx > 0, right = tx < im.NTX - 1;
+    for (int i = tid; i < 2 * NW + 2 * TH; i += kThreads) {
+        if (i < 2 * NW) {
+            const int side = i / NW, w = i % NW;
+            if ((side == 0 && !top) || (side == 1 && !bot))
+                continue;
+            const int r = side ? TH - 1 : 0, R = r / BH;
+            const uint32_t m = t.M[r * NW + w];
+            const uint32_t mL = w ? t.M[r * NW + w - 1] : 0u;
+            uint32_t starts = m & ~((m << 1) | (mL >> 31));
+            while (starts) {
+                const int bb = __ffs(starts) - 1;
+                starts &= starts - 1u;
+                const int32_t comp = t.RT[node_at(t, R, (w << 5) + bb)];
+                atomicOr(&t.BFB[comp >> 5], 1u << (comp & 31));
+            }
+        } else {
+            const int q = i - 2 * NW, side = q / TH, r = q % TH;
+            if ((side == 0 && !left) || (side == 1 && !right))
+                continue;
+            const int c = side ? TW - 1 : 0;
+            if (!((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u))
+                continue;
+            const int32_t comp = t.RT[node_at(t, r / BH, c)];
+            atomicOr(&t.BFB[comp >> 5], 1u << (comp & 31));
+        }
+    }
+    __syncthreads();
+    const int32_t n_bound = popcount_prefix(t.BFB, t.BFP, (n_comp + 31) >> 5);
+    for (int c = tid; c < n_comp; c += kThreads) {
+        if (!((t.BFB[c >> 5] >> (c & 31)) & 1u)) {
+            const int32_t key = t.P[c];
+            atomicOr(&t.RK[key >> 5], 1u << (key & 31));
+            atomicAdd(&t.rowcnt[key / TW], 1);
+        }
+    }
+    __syncthreads();
+
+    // 7. exports
+    const int64_t cbase = (int64_t)ti * G::CAP;
+    for (int c = tid; c < n_comp; c += kThreads) {
+        if ((t.BFB[c >> 5] >> (c & 31)) & 1u) {
+            const int32_t j = rank_of(t.BFB, t.BFP, c);
+            const int32_t key = t.P[c];
+            const int kr = key / TW, kc = key % TW;
+            const uint32_t id = (uint32_t)(cbase + j);
+            const uint32_t gkey = (uint32_t)((y0 + kr) * im.W + x0 + kc);
+            im.bkey[id] = (uint16_t)key;
+            im.bval[id] = popc_before(&t.RK[kr * NW], kc);
+            im.uf[id] = ((uint64_t)gkey << 32) | id;
+        }
+    }
+    // edge buffers: boundary index of the component of every edge pixel
+    for (int i = tid; i < 2 * TW + 2 * TH; i += kThreads) {
+        int r, c;
+        uint16_t *dst;
+        bool on;
+        if (i < 2 * TW) {
+            const int side = i / TW;
+            c = i % TW;
+            r = side ? TH - 1 : 0;
+            on = (side ? bot : top) && x0 + c < im.W;
+            dst = im.he + ((int64_t)ty * 2 + side) * im.W + x0 + c;
+        } else {
+            const int q = i - 2 * TW, side = q / TH;
+            r = q % TH;
+            c = side ? TW - 1 : 0;
+            on = (side ? right : left) && y0 + r < im.H;
+            dst = im.ve + ((int64_t)tx * 2 + side) * im.H + y0 + r;
+        }
+        if (!on)
+            continue;
+        uint16_t v = kNone;
+        if ((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u)
+            v = (uint16_t)rank_of(t.BFB, t.BFP, t.RT[node_at(t, r / BH, c)]);
+        *dst = v;
+    }
+    for (int r = tid; r < TH; r += kThreads)
+        if (y0 + r < im.H)
+            im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.rowcnt[r];
+    uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
+    for (int k = tid; k < n_runs; k += kThreads)
+        grt[k] = t.RT[k];
+    uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
+    for (int c = tid; c < n_comp; c += kThreads)
+        gck[c] = (uint16_t)t.P[c];
+    uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
+    for (int i = tid; i < ((n_comp + 31) >> 5); i += kThreads)
+        gcb[i] = t.BFB[i];
+    if (tid == 0) {
+        im.tcnt[ti * 4 + 0] = n_runs;
+        im.tcnt[ti * 4 + 1] = n_comp;
+        im.tcnt[ti * 4 + 2] = n_bound;
+    }
+}
+
+// ------------------------------------------------------------------------
+// K2: boundary merge (Algorithm 7's boundary loop with Algorithm 8's
+// merger).  One item per 32-pixel segment of every shared tile edge.  The
+// two pixel lines facing each other across the edge are treated as two rows
+// of runs.  Runs are cut where a perpendicular tile edge crosses the line,
+// so every run lies in one tile and belongs to one local component; then
+// every pair of runs that touch (8-conn: also diagonally) is united once:
+//   U1 at the first position of their overlap,
+//   U2 where the earlier line's run starts just after the later line's run
+//      ends (diagonal),
+//   U3 where the later line's run starts just after the earlier line's run
+//      ends (diagonal).
+// At a cut U1 and U3 can both hold, so they are walked separately.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t line_mask(const uint16_t *line, int from, int n) {
+    uint32_t m = 0;
+    for (int i = 0; i < 32; i++)
+        if (from + i < n && line[from + i] != kNone)
+            m |= 1u << i;
+    return m;
+}
+
+__device__ __forceinline__ bool fg_at(const uint16_t *line, int pos, int n) {
+    return pos >= 0 && pos < n && line[pos] != kNone;
+}
+
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
+    using G = Geo<NSR, TW, BH>;
+    constexpr int TH = G::TH;
+    const int32_t item = blockIdx.x * kThreads + threadIdx.x;
+    const Img &im = find_img(b, item, kEdge);
+    int32_t e = item - im.edge0;
+    const int32_t nxs = (im.W + 31) >> 5, nys = (im.H + 31) >> 5;
+    const int32_t nH = (im.NTY - 1) * nxs, nV = (im.NTX - 1) * nys;
+    if (e < 0 || e >= nH + nV)
+        return;
+    const bool conn8 = BH == 2;
+    const uint16_t *lo, *hi;   // lo: the line of the later tiles, hi: of the earlier ones
+    int from, n, later_t, period;
+    const bool horiz = e < nH;
+    if (horiz) {
+        later_t = 1 + e / nxs;       // tile row of the lower tiles
+        from = (e % nxs) << 5;
+        n = im.W;
+        period = TW;
+        lo = im.he + ((int64_t)later_t * 2 + 0) * im.W;
+        hi = im.he + ((int64_t)(later_t - 1) * 2 + 1) * im.W;
+    } else {
+        e -= nH;
+        later_t = 1 + e / nys;       // tile column of the right tiles
+        from = (e % nys) << 5;
+        n = im.H;
+        period = TH;
+        lo = im.ve + ((int64_t)later_t * 2 + 0) * im.H;
+        hi = im.ve + ((int64_t)(later_t - 1) * 2 + 1) * im.H;
+    }
+    const int earlier_t = later_t - 1;
+    // cut[c]: a perpendicular tile edge lies between positions c-1 and c
+    uint32_t cut = 0u;
+    for (int c = 0; c < 32; c++)
+        if ((from + c) % period == 0)
+            cut |= 1u << c;
+    const uint32_t cutn = (cut >> 1) | (((from + 32) % period == 0) ? 0x80000000u : 0u);
+    const uint32_t m = line_mask(lo, from, n), up = line_mask(hi, from, n);
+    const uint32_t mL = fg_at(lo, from - 1, n) ? 1u : 0u, uL = fg_at(hi, from - 1, n) ? 1u : 0u;
+    const uint32_t mR = fg_at(lo, from + 32, n) ? 1u : 0u, uR = fg_at(hi, from + 32, n) ? 1u : 0u;
+    const uint32_t mp = ((m << 1) | mL) & ~cut;         // same run continues from c-1
+    const uint32_t upp = (up << 1) | uL;                // earlier line at c-1
+    const uint32_t mn = ((m >> 1) | (mR << 31)) & ~cutn; // same run continues to c+1
+    const uint32_t un = (up >> 1) | (uR << 31);          // earlier line at c+1
+    const uint32_t o = m & up;
+    const uint32_t u1 = o & ~(mp & upp & ~cut);
+    uint32_t u2 = 0u, u3 = 0u;
+    if (conn8) {
+        u2 = m & ~mn & un & ~(up & ~cutn);             // earlier run starts at c+1
+        u3 = m & ~mp & upp & ~(up & ~cut);             // earlier run ends at c-1
+    }
+    uint64_t cm = (uint64_t)u1 | ((uint64_t)u3 << 32);
+    for (int pass = 0; pass < 2; pass++) {
+        while (cm) {
+            const int bit = __ffsll((unsigned long long)cm) - 1;
+            cm &= cm - 1;
+            const int c = bit & 31;
+            const int d = pass ? 1 : ((bit >> 5) ? -1 : 0);
+            const int pa = from + c, pb = pa + d;
+            uint32_t ida, idb;
+            if (horiz) {
+                ida = (uint32_t)(((int64_t)later_t * im.NTX + pa / TW) * G::CAP + lo[pa]);
+                idb = (uint32_t)(((int64_t)earlier_t * im.NTX + pb / TW) * G::CAP + hi[pb]);
+            } else {
+                ida = (uint32_t)(((int64_t)(pa / TH) * im.NTX + later_t) * G::CAP + lo[pa]);
+                idb = (uint32_t)(((int64_t)(pb / TH) * im.NTX + earlier_t) * G::CAP + hi[pb]);
+            }
+            rem_union_global(im.uf, ida, idb);
+        }
+        cm = u2;
+    }
+}
+
+// ------------------------------------------------------------------------
+// K3a: flatten the boundary components of one tile; a component that is its
+// set's root owns the set's first raster pixel.  Adds those roots to the
+// segment counts and turns their "interior roots before" into the offset
+// inside their row segment.
+// ------------------------------------------------------------------------
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
+    using G = Geo<NSR, TW, BH>;
+    constexpr int NW = G::NW, TH = G::TH;
+    __shared__ uint32_t RK[G::NM];
+    __shared__ int32_t rowc[TH];
+    const Img &im = find_img(b, blockIdx.x, kTile);
+    const int ti = blockIdx.x - im.tile0;
+    const int n = im.tcnt[ti * 4 + 2];
+    if (n == 0)
+        return;
+    const int ty = ti / im.NTX, tx = ti % im.NTX;
+    const int y0 = ty * TH;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < G::NM; i += kThreads)
+        RK[i] = 0u;
+    for (int r = tid; r < TH; r += kThreads)
+        rowc[r] = 0;
+    __syncthreads();
+    const int64_t cbase = (int64_t)ti * G::CAP;
+    for (int j = tid; j < n; j += kThreads) {
+        const uint32_t id = (uint32_t)(cbase + j);
+        const bool is = find_compress_global(im.uf, id) == id;
+        im.broot[id] = is;
+        if (is) {
+            const int key = im.bkey[id];
+            atomicOr(&RK[key >> 5], 1u << (key & 31));
+            atomicAdd(&rowc[key / TW], 1);
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += kThreads) {
+        const uint32_t id = (uint32_t)(cbase + j);
+        if (im.broot[id]) {
+            const int key = im.bkey[id];
+            im.bval[id] += popc_before(&RK[(key / TW) * NW], key % TW);
+        }
+    }
+    for (int r = tid; r < TH; r += kThreads)
+        if (rowc[r] && y0 + r < im.H)
+            im.seg[(int64_t)(y0 + r) * im.NTX + tx] += rowc[r];
+}
+
+// ------------------------------------------------------------------------
+// K4a / K4b: exclusive scan of the segment counts in raster order.
+// ------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_scan_blocks(Batch b) {
     const Img &im = find_img(b, blockIdx.x, kScan);
     const int c = blockIdx.x - im.scan0;
@@ -690,175 +850,141 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(Batch b) {
 }
 
 // ------------------------------------------------------------------------
-// K3b: final label of every boundary root: 1 + roots before its segment +
-// roots before it inside the segment.  Written to the boundary list and to
-// labels[g] (read by other tiles' non-root boundary components in K5).
+// K3b: final label of every root boundary component: 1 + roots before its
+// segment + its offset inside the segment.
 // ------------------------------------------------------------------------
-template <int TH, int TW>
+template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_publish(Batch b) {
-    using G = Geo<TH, TW>;
+    using G = Geo<NSR, TW, BH>;
+    constexpr int TH = G::TH;
     const Img &im = find_img(b, blockIdx.x, kTile);
     const int ti = blockIdx.x - im.tile0;
-    const int n = im.bl_cnt[ti];
+    const int n = im.tcnt[ti * 4 + 2];
     const int ty = ti / im.NTX, tx = ti % im.NTX;
-    int32_t *bidx = im.bl_idx + (int64_t)ti * G::CAP;
-    int32_t *bval = im.bl_val + (int64_t)ti * G::CAP;
+    const int64_t cbase = (int64_t)ti * G::CAP;
     for (int j = threadIdx.x; j < n; j += kThreads) {
-        int32_t v = bidx[j];
-        if (!(v & kRootFlag))
+        const uint32_t id = (uint32_t)(cbase + j);
+        if (!im.broot[id])
             continue;
-        int32_t s = v & kLocalMask;
-        int64_t sg = (int64_t)(ty * TH + s / TW) * im.NTX + tx;
-        int32_t F = 1 + im.seg[sg] + im.blk[sg / kScanChunk] + bval[j];
-        bval[j] = F;
-        im.labels[gidx<TH, TW>(im, ty, tx, s)] = F;
+        const int key = im.bkey[id];
+        const int64_t sg = (int64_t)(ty * TH + key / TW) * im.NTX + tx;
+        im.bval[id] = 1 + im.seg[sg] + im.blk[sg / kScanChunk] + im.bval[id];
     }
 }
 
 // ------------------------------------------------------------------------
-// K5: labeling pass.  Rebuild the tile labeling, give every local component
-// its final label, write all pixels with 16-byte stores.
+// K5: labeling pass.  Rebuild the node numbering from the stored bitmask,
+// give every local component its final label, write all pixels with
+// 16-byte stores.
 // ------------------------------------------------------------------------
-template <int TH, int TW>
+template <int NSR, int TW, int BH>
+struct RelabelLds : RunLds<NSR, TW, BH> {
+    using G = Geo<NSR, TW, BH>;
+    int32_t CF[G::RCAP];    // final label of each local component
+    int32_t RF[G::RCAP];    // final label of each node
+    uint32_t RM[G::NM];     // keys of components that are global roots (bit per pixel)
+    uint32_t BFB[G::RW];
+    int32_t BFP[G::RW];
+    int32_t rowbase[G::TH];
+};
+
+template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_relabel(Batch b) {
-    using G = Geo<TH, TW>;
-    constexpr int NW = G::NW;
-    __shared__ TileLds<TH, TW> t;
-    __shared__ int32_t rowbase[TH];
+    using G = Geo<NSR, TW, BH>;
+    constexpr int NW = G::NW, TH = G::TH;
+    __shared__ RelabelLds<NSR, TW, BH> t;
     const Img &im = find_img(b, blockIdx.x, kTile);
     const int ti = blockIdx.x - im.tile0;
     const int ty = ti / im.NTX, tx = ti % im.NTX;
     const int y0 = ty * TH, x0 = tx * TW;
     const int tid = threadIdx.x;
+    const int n_runs = im.tcnt[ti * 4 + 0];
+    const int n_comp = im.tcnt[ti * 4 + 1];
+    const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+#pragma unroll
+    for (int k = 0; k < G::MPT; k++) {
+        const int i = tid + k * kThreads;
+        if (i < G::NM) {
+            t.M[i] = gmask[i];
+            t.RM[i] = 0u;
+        }
+    }
     for (int r = tid; r < TH; r += kThreads) {
         int32_t v = 0;
         if (y0 + r < im.H) {
-            int64_t sg = (int64_t)(y0 + r) * im.NTX + tx;
+            const int64_t sg = (int64_t)(y0 + r) * im.NTX + tx;
             v = im.seg[sg] + im.blk[sg / kScanChunk];
         }
-        rowbase[r] = v;
+        t.rowbase[r] = v;
     }
-    tile_label<TH, TW>(t, im, y0, x0);
+    const int ncw = (n_comp + 31) >> 5;
+    const uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
+    for (int i = tid; i < ncw; i += kThreads)
+        t.BFB[i] = gcb[i];
+    __syncthreads();
+    number_runs<NSR, TW, BH>(t);
+    popcount_prefix(t.BFB, t.BFP, ncw);
+    __syncthreads();
 
-    // boundary components: final label from the boundary list (own roots)
-    // or from the global root's published label
-    const int n = im.bl_cnt[ti];
-    const int32_t *bidx = im.bl_idx + (int64_t)ti * G::CAP;
-    const int32_t *bval = im.bl_val + (int64_t)ti * G::CAP;
-    for (int j = tid; j < n; j += kThreads) {
-        int32_t v = bidx[j];
-        int32_t s = v & kLocalMask;
-        int32_t F;
-        if (v & kRootFlag) {
-            F = bval[j];
-            atomicOr(&t.A[s >> 5], 1u << (s & 31));
+    // component labels: boundary components from the merged global sets,
+    // interior components ranked inside their row segment
+    const uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
+    const int64_t cbase = (int64_t)ti * G::CAP;
+    for (int c = tid; c < n_comp; c += kThreads) {
+        const int key = gck[c];
+        if ((t.BFB[c >> 5] >> (c & 31)) & 1u) {
+            const uint32_t id = (uint32_t)(cbase + rank_of(t.BFB, t.BFP, c));
+            if (im.broot[id]) {
+                t.CF[c] = im.bval[id];
+                atomicOr(&t.RM[key >> 5], 1u << (key & 31));
+            } else {
+                t.CF[c] = im.bval[(uint32_t)im.uf[id]];
+            }
         } else {
-            int32_t root = im.labels[gidx<TH, TW>(im, ty, tx, s)];
-            F = im.labels[root];
-        }
-        t.P[s] = -F - 1;
-    }
-    __syncthreads();
-    // interior roots join the root mask
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t bits = t.S[u];
-            while (bits) {
-                int bb = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                int32_t s = r * TW + (w << 5) + bb;
-                if (t.P[s] == s)
-                    atomicOr(&t.A[u], 1u << bb);
-            }
+            atomicOr(&t.RM[key >> 5], 1u << (key & 31));
+            t.CF[c] = ~key;
         }
     }
     __syncthreads();
-    // interior roots: rank inside their row segment
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t bits = t.S[u];
-            while (bits) {
-                int bb = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                int32_t s = r * TW + (w << 5) + bb;
-                if (t.P[s] == s) {
-                    int32_t F = 1 + rowbase[r] + popc_before(&t.A[r * NW], (w << 5) + bb);
-                    t.P[s] = -F - 1;
-                }
-            }
+    for (int c = tid; c < n_comp; c += kThreads) {
+        const int32_t v = t.CF[c];
+        if (v < 0) {
+            const int key = ~v, kr = key / TW;
+            t.CF[c] = 1 + t.rowbase[kr] + popc_before(&t.RM[kr * NW], key % TW);
         }
     }
     __syncthreads();
-    // other run starts take their root's final label
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        int u = tid + k * kThreads;
-        if (u < G::NU) {
-            int r = u / NW, w = u % NW;
-            uint32_t bits = t.S[u];
-            while (bits) {
-                int bb = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                int32_t s = r * TW + (w << 5) + bb;
-                int32_t p = t.P[s];
-                if (p >= 0)
-                    t.P[s] = t.P[p];
-            }
-        }
-    }
+    const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
+    for (int k = tid; k < n_runs; k += kThreads)
+        t.RF[k] = t.CF[grt[k]];
     __syncthreads();
 
-    // write: one tile row per wave instruction, 4 pixels (16 bytes) per lane
+    // write: one tile row segment of 256 pixels per wave instruction
     const int wave = tid >> 6, lane = tid & 63;
     const bool vec_ok = ((im.W & 3) == 0) && ((reinterpret_cast<uintptr_t>(im.labels) & 15u) == 0);
     for (int r = wave; r < TH; r += kThreads / 64) {
         const int y = y0 + r;
         if (y >= im.H)
             break;
+        const int R = r / BH;
         for (int q = lane; q < TW / 4; q += 64) {
             const int c0 = q * 4, x = x0 + c0;
             if (x >= im.W)
                 continue;
             const int w = c0 >> 5, b0 = c0 & 31;
-            uint32_t m = t.M[r * NW + w] >> b0;
-            uint32_t st = t.S[r * NW + w] >> b0;
-            int32_t cur = 0;
+            const uint32_t m = t.M[r * NW + w] >> b0;
+            const uint32_t s = t.S[R * NW + w];
+            const int32_t bs = t.base[R * NW + w] - 1;
             i32x4 o;
-            if (m & 1u)
-                cur = -t.P[run_start(t, r, c0)] - 1;
-            o.x = (m & 1u) ? cur : 0;
-            if (m & 2u) {
-                if (st & 2u)
-                    cur = -t.P[r * TW + c0 + 1] - 1;
-                o.y = cur;
-            } else {
-                o.y = 0;
-            }
-            if (m & 4u) {
-                if (st & 4u)
-                    cur = -t.P[r * TW + c0 + 2] - 1;
-                o.z = cur;
-            } else {
-                o.z = 0;
-            }
-            if (m & 8u) {
-                if (st & 8u)
-                    cur = -t.P[r * TW + c0 + 3] - 1;
-                o.w = cur;
-            } else {
-                o.w = 0;
-            }
+            o.x = (m & 1u) ? t.RF[bs + __popc(s & mask_le(b0))] : 0;
+            o.y = (m & 2u) ? t.RF[bs + __popc(s & mask_le(b0 + 1))] : 0;
+            o.z = (m & 4u) ? t.RF[bs + __popc(s & mask_le(b0 + 2))] : 0;
+            o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
             int32_t *dst = im.labels + (int64_t)y * im.W + x;
             if (vec_ok && x + 4 <= im.W) {
                 __builtin_nontemporal_store(o, reinterpret_cast<i32x4 *>(dst));
             } else {
-                int nn = im.W - x < 4 ? im.W - x : 4;
+                const int nn = im.W - x < 4 ? im.W - x : 4;
                 dst[0] = o.x;
                 if (nn > 1)
                     dst[1] = o.y;

@@ -68,8 +68,9 @@ def test_strerror_and_tiles():
     assert ccl.strerror(12345) == "unknown status"
     tiles = ccl.tile_configs()
     assert tiles[0] == (32, 256) and len(tiles) == ccl._lib.ccl_tile_count()
-    for th, tw in tiles:
-        assert tw % 32 == 0 and th * tw <= 65536
+    for nsr, tw in tiles:
+        assert tw % 64 == 0 and 2 * nsr * tw < 65536
+    assert ccl.tile_shape(0, 8) == (64, 256) and ccl.tile_shape(0, 4) == (32, 256)
 
 
 def test_workspace_bytes():
@@ -79,8 +80,9 @@ def test_workspace_bytes():
     a = ccl.workspace_bytes(1000, 1000)
     b = ccl.workspace_bytes(2000, 2000)
     assert 0 < a < b
-    # edge buffers + boundary lists + segment counts: well under the labels' own size
-    assert ccl.workspace_bytes(21568, 21568) < 21568 * 21568
+    # worst-case per-tile capacities: below the int32 labels' own size
+    assert ccl.workspace_bytes(21568, 21568) < 4 * 21568 * 21568
+    assert ccl.workspace_bytes(21568, 21568, conn=4) < 4 * 21568 * 21568
     both = ccl.batch_workspace_bytes([(1000, 1000), (2000, 2000)])
     assert both >= a + b - 1024
 
