@@ -135,41 +135,35 @@ __device__ __forceinline__ T acas(T *p, T expect, T v) {
 }
 
 // Rem's union with splicing (Algorithm 2), safe for concurrent callers as in
-// Algorithm 8: a root is linked by a CAS that succeeds only while it is
-// still a root; splices are atomic stores.  Every store writes a value
-// smaller than the node's own, so the forest stays acyclic and each root is
-// its set's smallest element.  Each iteration returns, moves rx or ry to a
-// strictly smaller node, or retries a link that another caller's successful
-// link made fail (with the value the CAS observed), so the loop ends.
+// Algorithm 8.  Each step takes the side whose parent is larger (node n with
+// parent pn, other side's parent q < pn) and tries one compare-and-swap
+// P[n]: pn -> q.  If n is a root (pn == n) a success is the link and ends
+// the union; otherwise a success is the splice and the step moves up to pn.
+// A failed CAS means another caller changed P[n]; the step re-reads it.
+// Every successful CAS lowers an entry (q < pn <= n), so there are finitely
+// many of them, every root stays its set's smallest node, and the loop ends.
+// The splice done by CAS rather than a plain store only skips a splice that
+// a concurrent change made stale.
 template <int S>
 __device__ void rem_union(int32_t *P, int32_t x, int32_t y) {
     int32_t rx = x, ry = y;
     int32_t px = aload<S>(P + rx);
     int32_t py = aload<S>(P + ry);
     while (px != py) {
-        if (px > py) {
-            if (px == rx) {
-                int32_t seen = acas<S>(P + rx, rx, py);
-                if (seen == rx)
-                    return;
-                px = seen;
-                continue;
-            }
-            astore<S>(P + rx, py);
-            rx = px;
-            px = aload<S>(P + rx);
-        } else {
-            if (py == ry) {
-                int32_t seen = acas<S>(P + ry, ry, px);
-                if (seen == ry)
-                    return;
-                py = seen;
-                continue;
-            }
-            astore<S>(P + ry, px);
-            ry = py;
-            py = aload<S>(P + ry);
-        }
+        const bool xs = px > py;
+        const int32_t n = xs ? rx : ry;
+        const int32_t pn = xs ? px : py;
+        const int32_t q = xs ? py : px;
+        const int32_t seen = acas<S>(P + n, pn, q);
+        const bool ok = seen == pn;
+        if (ok && pn == n)
+            return;
+        const int32_t nn = ok ? pn : n;
+        const int32_t np = aload<S>(P + nn);
+        rx = xs ? nn : rx;
+        px = xs ? np : px;
+        ry = xs ? ry : nn;
+        py = xs ? py : np;
     }
 }
 
@@ -182,29 +176,20 @@ __device__ void rem_union_global(uint64_t *P, uint32_t x, uint32_t y) {
     uint64_t px = aload<S>(P + rx);
     uint64_t py = aload<S>(P + ry);
     while (px != py) {
-        if (px > py) {
-            if ((uint32_t)px == rx) {
-                uint64_t seen = acas<S>(P + rx, px, py);
-                if (seen == px)
-                    return;
-                px = seen;
-                continue;
-            }
-            astore<S>(P + rx, py);
-            rx = (uint32_t)px;
-            px = aload<S>(P + rx);
-        } else {
-            if ((uint32_t)py == ry) {
-                uint64_t seen = acas<S>(P + ry, py, px);
-                if (seen == py)
-                    return;
-                py = seen;
-                continue;
-            }
-            astore<S>(P + ry, px);
-            ry = (uint32_t)py;
-            py = aload<S>(P + ry);
-        }
+        const bool xs = px > py;
+        const uint32_t n = xs ? rx : ry;
+        const uint64_t pn = xs ? px : py;
+        const uint64_t q = xs ? py : px;
+        const uint64_t seen = acas<S>(P + n, pn, q);
+        const bool ok = seen == pn;
+        if (ok && (uint32_t)pn == n)
+            return;
+        const uint32_t nn = ok ? (uint32_t)pn : n;
+        const uint64_t np = aload<S>(P + nn);
+        rx = xs ? nn : rx;
+        px = xs ? np : px;
+        ry = xs ? ry : nn;
+        py = xs ? py : np;
     }
 }
 
@@ -400,10 +385,9 @@ struct ScanLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
     int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
     uint16_t RT[G::RCAP];   // component ordinal of each node
-    uint32_t RFB[G::RW];    // root nodes (bit per node)
+    uint16_t SP[G::RCAP];   // start of each node: block row * TW + column
+    uint32_t RFB[G::RW];    // root nodes (bit per node); later boundary components (bit per component)
     int32_t RFP[G::RW];
-    uint32_t BFB[G::RW];    // boundary components (bit per component)
-    int32_t BFP[G::RW];
     uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
     int32_t rowcnt[G::TH];
 };
@@ -436,14 +420,26 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     }
     for (int r = tid; r < TH; r += kThreads)
         t.rowcnt[r] = 0;
-    for (int i = tid; i < G::RW; i += kThreads) {
+    for (int i = tid; i < G::RW; i += kThreads)
         t.RFB[i] = 0u;
-        t.BFB[i] = 0u;
-    }
     __syncthreads();
 
-    // 2. block runs and their ordinals
+    // 2. block runs, their ordinals and start positions
     const int32_t n_runs = number_runs<NSR, TW, BH>(t);
+#pragma unroll
+    for (int k = 0; k < G::UPT; k++) {
+        const int u = tid + k * kThreads;
+        if (u < G::NU) {
+            const int R = u / NW, w = u % NW;
+            uint32_t bits = t.S[u];
+            int32_t ord = t.base[u];
+            while (bits) {
+                const int bb = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                t.SP[ord++] = (uint16_t)(R * TW + (w << 5) + bb);
+            }
+        }
+    }
     for (int k = tid; k < n_runs; k += kThreads)
         t.P[k] = k;
     __syncthreads();
@@ -507,10 +503,22 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     }
     __syncthreads();
 
-    // 4. flatten; roots are numbered in node order (local components)
-    for (int k = tid; k < n_runs; k += kThreads)
-        if (find_compress<WG>(t.P, k) == k)
-            atomicOr(&t.RFB[k >> 5], 1u << (k & 31));
+    // 4. flatten; roots are numbered in node order (local components).  A
+    // wave handles 64 consecutive nodes, so its ballot is two words of the
+    // root bitmask.
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int k0 = 0; k0 < n_runs; k0 += kThreads) {
+        const int k = k0 + tid;
+        bool root = false;
+        if (k < n_runs)
+            root = find_compress<WG>(t.P, k) == k;
+        const uint64_t bal = __ballot(root);
+        const int wd = (k0 + wave * 64) >> 5;
+        if (lane == 0 && wd < G::RW)
+            t.RFB[wd] = (uint32_t)bal;
+        if (lane == 32 && wd + 1 < G::RW)
+            t.RFB[wd + 1] = (uint32_t)(bal >> 32);
+    }
     __syncthreads();
     const int32_t n_comp = popcount_prefix(t.RFB, t.RFP, (n_runs + 31) >> 5);
     __syncthreads();
@@ -522,41 +530,33 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     // the minimum over its nodes of the node's first pixel (top row first)
     for (int c = tid; c < n_comp; c += kThreads)
         t.P[c] = 0x7FFFFFFF;
+    for (int i = tid; i < G::RW; i += kThreads)
+        t.RFB[i] = 0u;  // from here on: boundary components
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        const int u = tid + k * kThreads;
-        if (u >= G::NU)
-            continue;
-        const int R = u / NW, w = u % NW;
-        uint32_t bits = t.S[u];
-        int32_t ord = t.base[u];
-        while (bits) {
-            const int bb = __ffs(bits) - 1;
-            bits &= bits - 1u;
-            int32_t key;
-            if (BH == 1) {
-                key = R * TW + (w << 5) + bb;
-            } else {
-                const int r0 = R * BH;
-                key = (r0 + 1) * TW + (w << 5) + bb;  // no top pixel: the run's start
-                int ww = w, from = bb;
-                for (;;) {
-                    const uint32_t tt = t.M[r0 * NW + ww] & mask_ge(from);
-                    const uint32_t gap = ~block_mask<NSR, TW, BH>(t.M, R, ww) & mask_ge(from);
-                    if (tt && (!gap || __ffs(tt) < __ffs(gap))) {
-                        key = r0 * TW + (ww << 5) + __ffs(tt) - 1;
-                        break;
-                    }
-                    if (gap || ww == NW - 1)
-                        break;
-                    ww++;
-                    from = 0;
+    for (int k = tid; k < n_runs; k += kThreads) {
+        const int sp = t.SP[k];
+        const int R = sp / TW, col = sp % TW;
+        int32_t key;
+        if (BH == 1) {
+            key = sp;
+        } else {
+            const int r0 = R * BH;
+            key = (r0 + 1) * TW + col;  // no top pixel: the run's start in the lower row
+            int ww = col >> 5, from = col & 31;
+            for (;;) {
+                const uint32_t tt = t.M[r0 * NW + ww] & mask_ge(from);
+                const uint32_t gap = ~block_mask<NSR, TW, BH>(t.M, R, ww) & mask_ge(from);
+                if (tt && (!gap || __ffs(tt) < __ffs(gap))) {
+                    key = r0 * TW + (ww << 5) + __ffs(tt) - 1;
+                    break;
                 }
+                if (gap || ww == NW - 1)
+                    break;
+                ww++;
+                from = 0;
             }
-            atomicMin(&t.P[t.RT[ord]], key);
-            ord++;
         }
+        atomicMin(&t.P[t.RT[k]], key);
     }
     __syncthreads();
 
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
                 const int bb = __ffs(starts) - 1;
                 starts &= starts - 1u;
                 const int32_t comp = t.RT[node_at(t, R, (w << 5) + bb)];
-                atomicOr(&t.BFB[comp >> 5], 1u << (comp & 31));
+                atomicOr(&t.RFB[comp >> 5], 1u << (comp & 31));
             }
         } else {
             const int q = i - 2 * NW, side = q / TH, r = q % TH;
@@ -585,13 +585,13 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             if (!((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u))
                 continue;
             const int32_t comp = t.RT[node_at(t, r / BH, c)];
-            atomicOr(&t.BFB[comp >> 5], 1u << (comp & 31));
+            atomicOr(&t.RFB[comp >> 5], 1u << (comp & 31));
         }
     }
     __syncthreads();
-    const int32_t n_bound = popcount_prefix(t.BFB, t.BFP, (n_comp + 31) >> 5);
+    const int32_t n_bound = popcount_prefix(t.RFB, t.RFP, (n_comp + 31) >> 5);
     for (int c = tid; c < n_comp; c += kThreads) {
-        if (!((t.BFB[c >> 5] >> (c & 31)) & 1u)) {
+        if (!((t.RFB[c >> 5] >> (c & 31)) & 1u)) {
             const int32_t key = t.P[c];
             atomicOr(&t.RK[key >> 5], 1u << (key & 31));
             atomicAdd(&t.rowcnt[key / TW], 1);
@@ -602,8 +602,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     // 7. exports
     const int64_t cbase = (int64_t)ti * G::CAP;
     for (int c = tid; c < n_comp; c += kThreads) {
-        if ((t.BFB[c >> 5] >> (c & 31)) & 1u) {
-            const int32_t j = rank_of(t.BFB, t.BFP, c);
+        if ((t.RFB[c >> 5] >> (c & 31)) & 1u) {
+            const int32_t j = rank_of(t.RFB, t.RFP, c);
             const int32_t key = t.P[c];
             const int kr = key / TW, kc = key % TW;
             const uint32_t id = (uint32_t)(cbase + j);
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             continue;
         uint16_t v = kNone;
         if ((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u)
-            v = (uint16_t)rank_of(t.BFB, t.BFP, t.RT[node_at(t, r / BH, c)]);
+            v = (uint16_t)rank_of(t.RFB, t.RFP, t.RT[node_at(t, r / BH, c)]);
         *dst = v;
     }
     for (int r = tid; r < TH; r += kThreads)
@@ -649,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
         gck[c] = (uint16_t)t.P[c];
     uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
     for (int i = tid; i < ((n_comp + 31) >> 5); i += kThreads)
-        gcb[i] = t.BFB[i];
+        gcb[i] = t.RFB[i];
     if (tid == 0) {
         im.tcnt[ti * 4 + 0] = n_runs;
         im.tcnt[ti * 4 + 1] = n_comp;
