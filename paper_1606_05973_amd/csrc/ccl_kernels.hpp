@@ -476,8 +476,9 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             u2 = m & ~mn & ~up & un;
             u3 = m & ~mp & ~up & upp;
         }
-        uint64_t cm = (uint64_t)(u1 | u3) | ((uint64_t)u2 << 32);
-        if (!cm)
+        uint64_t cm1 = (uint64_t)u1 | ((uint64_t)u3 << 32);  // partner at c (U1) or c-1 (U3)
+        uint32_t cm2 = u2;                                    // partner at c+1 (U2)
+        if (!cm1 && !cm2)
             continue;
         const uint32_t sR = t.S[u];
         const int32_t bR = t.base[u] - 1;
@@ -488,17 +489,51 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
         const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
         const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
         const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
-        while (cm) {
-            const int bit = __ffsll((unsigned long long)cm) - 1;
-            cm &= cm - 1;
-            const int c = bit & 31;
-            const int d = (bit >> 5) ? 1 : (((u1 >> c) & 1u) ? 0 : -1);
-            const int32_t a = bR + __popc(sR & mask_le(c));
-            const int p = c + d;
-            const uint32_t sp = p < 0 ? sUL : (p > 31 ? sUR : sU);
-            const int32_t bp = p < 0 ? bUL : (p > 31 ? bUR : bU);
-            const int32_t bb = bp + __popc(sp & mask_le(p & 31));
-            rem_union<WG>(t.P, a, bb);
+        // One flat loop: each lane steps its own union (one load pair and one
+        // CAS per step) and takes its next contact as soon as the current
+        // union ends, so lanes never wait for each other's unions.
+        bool busy = false;
+        int32_t rx = 0, ry = 0;
+        for (;;) {
+            if (!busy) {
+                if (!cm1 && !cm2)
+                    break;
+                int c, d;
+                if (cm1) {
+                    const int bit = __ffsll((unsigned long long)cm1) - 1;
+                    cm1 &= cm1 - 1;
+                    c = bit & 31;
+                    d = (bit >> 5) ? -1 : 0;
+                } else {
+                    c = __ffs(cm2) - 1;
+                    cm2 &= cm2 - 1u;
+                    d = 1;
+                }
+                rx = bR + __popc(sR & mask_le(c));
+                const int p = c + d;
+                const uint32_t sp = p < 0 ? sUL : (p > 31 ? sUR : sU);
+                const int32_t bp = p < 0 ? bUL : (p > 31 ? bUR : bU);
+                ry = bp + __popc(sp & mask_le(p & 31));
+                busy = true;
+            }
+            const int32_t px = aload<WG>(t.P + rx);
+            const int32_t py = aload<WG>(t.P + ry);
+            if (px == py) {
+                busy = false;
+                continue;
+            }
+            const bool xs = px > py;
+            const int32_t n = xs ? rx : ry;
+            const int32_t pn = xs ? px : py;
+            const int32_t seen = acas<WG>(t.P + n, pn, xs ? py : px);
+            if (seen == pn) {
+                if (pn == n) {
+                    busy = false;
+                    continue;
+                }
+                rx = xs ? pn : rx;
+                ry = xs ? ry : pn;
+            }
         }
     }
     __syncthreads();
@@ -735,25 +770,56 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
         u2 = m & ~mn & un & ~(up & ~cutn);             // earlier run starts at c+1
         u3 = m & ~mp & upp & ~(up & ~cut);             // earlier run ends at c-1
     }
-    uint64_t cm = (uint64_t)u1 | ((uint64_t)u3 << 32);
-    for (int pass = 0; pass < 2; pass++) {
-        while (cm) {
-            const int bit = __ffsll((unsigned long long)cm) - 1;
-            cm &= cm - 1;
-            const int c = bit & 31;
-            const int d = pass ? 1 : ((bit >> 5) ? -1 : 0);
-            const int pa = from + c, pb = pa + d;
-            uint32_t ida, idb;
-            if (horiz) {
-                ida = (uint32_t)(((int64_t)later_t * im.NTX + pa / TW) * G::CAP + lo[pa]);
-                idb = (uint32_t)(((int64_t)earlier_t * im.NTX + pb / TW) * G::CAP + hi[pb]);
+    uint64_t cm1 = (uint64_t)u1 | ((uint64_t)u3 << 32);  // partner at c (U1) or c-1 (U3)
+    uint32_t cm2 = u2;                                    // partner at c+1 (U2)
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+    uint64_t *P = im.uf;
+    // flat loop: one union step per iteration, next contact when one ends
+    bool busy = false;
+    uint32_t rx = 0, ry = 0;
+    for (;;) {
+        if (!busy) {
+            if (!cm1 && !cm2)
+                break;
+            int c, d;
+            if (cm1) {
+                const int bit = __ffsll((unsigned long long)cm1) - 1;
+                cm1 &= cm1 - 1;
+                c = bit & 31;
+                d = (bit >> 5) ? -1 : 0;
             } else {
-                ida = (uint32_t)(((int64_t)(pa / TH) * im.NTX + later_t) * G::CAP + lo[pa]);
-                idb = (uint32_t)(((int64_t)(pb / TH) * im.NTX + earlier_t) * G::CAP + hi[pb]);
+                c = __ffs(cm2) - 1;
+                cm2 &= cm2 - 1u;
+                d = 1;
             }
-            rem_union_global(im.uf, ida, idb);
+            const int pa = from + c, pb = pa + d;
+            if (horiz) {
+                rx = (uint32_t)(((int64_t)later_t * im.NTX + pa / TW) * G::CAP + lo[pa]);
+                ry = (uint32_t)(((int64_t)earlier_t * im.NTX + pb / TW) * G::CAP + hi[pb]);
+            } else {
+                rx = (uint32_t)(((int64_t)(pa / TH) * im.NTX + later_t) * G::CAP + lo[pa]);
+                ry = (uint32_t)(((int64_t)(pb / TH) * im.NTX + earlier_t) * G::CAP + hi[pb]);
+            }
+            busy = true;
         }
-        cm = u2;
+        const uint64_t px = aload<AG>(P + rx);
+        const uint64_t py = aload<AG>(P + ry);
+        if (px == py) {
+            busy = false;
+            continue;
+        }
+        const bool xs = px > py;
+        const uint32_t n = xs ? rx : ry;
+        const uint64_t pn = xs ? px : py;
+        const uint64_t seen = acas<AG>(P + n, pn, xs ? py : px);
+        if (seen == pn) {
+            if ((uint32_t)pn == n) {
+                busy = false;
+                continue;
+            }
+            rx = xs ? (uint32_t)pn : rx;
+            ry = xs ? ry : (uint32_t)pn;
+        }
     }
 }
 
