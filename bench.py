@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile configuration id (0 = default)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB (a plain copy kernel "
+                         "of known size, used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,6 +110,14 @@ def main():
     ccl.profile(False)
     phases, ncalls = ccl.profile_read()
     ms_step = start.elapsed_time(end) / args.steps
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     px = S * S
     gpx = px / (ms_step * 1e-3) / 1e9
     phase_ms = {k: v / max(ncalls, 1) for k, v in phases.items()}
