@@ -216,7 +216,7 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     const dim3 blk(kThreads);
     PhaseMarks pm(s);
     pm.mark();
-    hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     pm.mark();
     if (edges > 0)
         hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((edges + kThreads - 1) / kThreads)), blk, 0, s, b);
@@ -229,7 +229,7 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     pm.mark();
     hipLaunchKernelGGL((k_publish<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_relabel<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    hipLaunchKernelGGL((k_relabel<NSR, TW, BH>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }

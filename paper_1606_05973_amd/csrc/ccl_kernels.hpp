@@ -34,7 +34,8 @@
 
 namespace ccl {
 
-constexpr int kThreads = 256;       // threads per workgroup (4 wave64)
+constexpr int kThreads = 256;       // threads per workgroup of the small kernels (4 wave64)
+constexpr int kTileThreads = 512;   // threads per workgroup of the tile scan and labeling pass (8 wave64)
 constexpr uint16_t kNone = 0xFFFFu;  // background pixel in the edge buffers
 constexpr int kScanChunk = 4096;     // segment counts per scan block (256 x 16)
 
@@ -104,8 +105,6 @@ struct Geo {
     static constexpr int NW = TW / 32;
     static constexpr int NU = NSR * NW;                        // (block row, word) units
     static constexpr int NM = TH * NW;                         // mask words
-    static constexpr int UPT = (NU + kThreads - 1) / kThreads;
-    static constexpr int MPT = (NM + kThreads - 1) / kThreads;
     static constexpr int RCAP = NSR * (TW / 2);                // most nodes a tile can hold
     static constexpr int RW = RCAP / 32;                       // words of a node/component bitmask
     static constexpr int CAP = 2 * (TH + TW);                  // > pixels on the tile perimeter
@@ -274,10 +273,11 @@ __device__ __forceinline__ uint32_t load_word(const Img &im, int y, int x) {
     return m;
 }
 
-// Exclusive prefix sum of v over the workgroup; *total gets the sum.
-// Contains two barriers; every thread must call it.
+// Exclusive prefix sum of v over a workgroup of NT threads; *total gets the
+// sum.  Contains two barriers; every thread must call it.
+template <int NT>
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
-    __shared__ int32_t wsum[kThreads / 64];
+    __shared__ int32_t wsum[NT / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int32_t incl = v;
 #pragma unroll
@@ -291,7 +291,7 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *tota
     __syncthreads();
     int32_t before = 0, all = 0;
 #pragma unroll
-    for (int k = 0; k < kThreads / 64; k++) {
+    for (int k = 0; k < NT / 64; k++) {
         int32_t s = wsum[k];
         before += (k < wv) ? s : 0;
         all += s;
@@ -301,14 +301,15 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *tota
     return before + incl - v;
 }
 
-// Exclusive popcount prefix of n bitmask words (n may exceed kThreads).
+// Exclusive popcount prefix of n bitmask words (n may exceed NT).
+template <int NT>
 __device__ __forceinline__ int32_t popcount_prefix(const uint32_t *bits, int32_t *pref, int n) {
     int32_t carry = 0;
-    for (int base = 0; base < n; base += kThreads) {
+    for (int base = 0; base < n; base += NT) {
         int i = base + threadIdx.x;
         int32_t v = i < n ? __popc(bits[i]) : 0;
         int32_t tot;
-        int32_t ex = block_exclusive_scan(v, &tot);
+        int32_t ex = block_exclusive_scan<NT>(v, &tot);
         if (i < n)
             pref[i] = carry + ex;
         carry += tot;
@@ -351,14 +352,15 @@ __device__ __forceinline__ int32_t node_at(const RunLds<NSR, TW, BH> &t, int R, 
 }
 
 // Fills S and base from M; returns the number of nodes (same on all threads).
-template <int NSR, int TW, int BH>
+template <int NSR, int TW, int BH, int NT>
 __device__ int32_t number_runs(RunLds<NSR, TW, BH> &t) {
     using G = Geo<NSR, TW, BH>;
     constexpr int NW = G::NW;
+    constexpr int UPT = (G::NU + NT - 1) / NT;
     int32_t carry = 0;
 #pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        const int u = threadIdx.x + k * kThreads;
+    for (int k = 0; k < UPT; k++) {
+        const int u = threadIdx.x + k * NT;
         int32_t cnt = 0;
         if (u < G::NU) {
             const int R = u / NW, w = u % NW;
@@ -369,7 +371,7 @@ __device__ int32_t number_runs(RunLds<NSR, TW, BH> &t) {
             cnt = __popc(s);
         }
         int32_t tot;
-        int32_t ex = block_exclusive_scan(cnt, &tot);
+        int32_t ex = block_exclusive_scan<NT>(cnt, &tot);
         if (u < G::NU)
             t.base[u] = carry + ex;
         carry += tot;
@@ -393,8 +395,15 @@ struct ScanLds : RunLds<NSR, TW, BH> {
 };
 
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
+__global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     using G = Geo<NSR, TW, BH>;
+    constexpr int NT = kTileThreads;
+    constexpr int MPT = (G::NM + NT - 1) / NT;
+    constexpr int UPT = (G::NU + NT - 1) / NT;
+    // threads per (block row, word) unit in the union step, and the bits each takes
+    constexpr int LPU = NT >= G::NU ? NT / G::NU : 1;
+    constexpr int UPT2 = (G::NU * LPU + NT - 1) / NT;
+    static_assert(NT < G::NU || NT % G::NU == 0, "unit count must divide the thread count");
     constexpr int NW = G::NW, TH = G::TH;
     constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
     __shared__ ScanLds<NSR, TW, BH> t;
@@ -408,8 +417,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     // 1. foreground masks (kept in LDS and stored for the labeling pass)
     uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
 #pragma unroll
-    for (int k = 0; k < G::MPT; k++) {
-        const int i = tid + k * kThreads;
+    for (int k = 0; k < MPT; k++) {
+        const int i = tid + k * NT;
         if (i < G::NM) {
             const int r = i / NW, w = i % NW;
             uint32_t m = load_word(im, y0 + r, x0 + (w << 5));
@@ -418,17 +427,17 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             t.RK[i] = 0u;
         }
     }
-    for (int r = tid; r < TH; r += kThreads)
+    for (int r = tid; r < TH; r += NT)
         t.rowcnt[r] = 0;
-    for (int i = tid; i < G::RW; i += kThreads)
+    for (int i = tid; i < G::RW; i += NT)
         t.RFB[i] = 0u;
     __syncthreads();
 
     // 2. block runs, their ordinals and start positions
-    const int32_t n_runs = number_runs<NSR, TW, BH>(t);
+    const int32_t n_runs = number_runs<NSR, TW, BH, NT>(t);
 #pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        const int u = tid + k * kThreads;
+    for (int k = 0; k < UPT; k++) {
+        const int u = tid + k * NT;
         if (u < G::NU) {
             const int R = u / NW, w = u % NW;
             uint32_t bits = t.S[u];
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             }
         }
     }
-    for (int k = tid; k < n_runs; k += kThreads)
+    for (int k = tid; k < n_runs; k += NT)
         t.P[k] = k;
     __syncthreads();
 
@@ -451,9 +460,10 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     // lower one's end, U3 (8-conn) where the lower run starts just right of
     // the upper one's end.
 #pragma unroll
-    for (int k = 0; k < G::UPT; k++) {
-        const int u = tid + k * kThreads;
-        if (u >= G::NU)
+    for (int k = 0; k < UPT2; k++) {
+        const int v = tid + k * NT;
+        const int u = v % G::NU, h = v / G::NU;
+        if (h >= LPU)
             continue;
         const int R = u / NW, w = u % NW;
         if (R == 0)
@@ -476,8 +486,11 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             u2 = m & ~mn & ~up & un;
             u3 = m & ~mp & ~up & upp;
         }
-        uint64_t cm1 = (uint64_t)u1 | ((uint64_t)u3 << 32);  // partner at c (U1) or c-1 (U3)
-        uint32_t cm2 = u2;                                    // partner at c+1 (U2)
+        // this thread's share of the word's contact positions
+        constexpr int PART = 32 / LPU;
+        const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
+        uint64_t cm1 = (uint64_t)(u1 & mine) | ((uint64_t)(u3 & mine) << 32);  // partner at c (U1) or c-1 (U3)
+        uint32_t cm2 = u2 & mine;                                              // partner at c+1 (U2)
         if (!cm1 && !cm2)
             continue;
         const uint32_t sR = t.S[u];
@@ -542,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
     // wave handles 64 consecutive nodes, so its ballot is two words of the
     // root bitmask.
     const int wave = tid >> 6, lane = tid & 63;
-    for (int k0 = 0; k0 < n_runs; k0 += kThreads) {
+    for (int k0 = 0; k0 < n_runs; k0 += NT) {
         const int k = k0 + tid;
         bool root = false;
         if (k < n_runs)
@@ -555,20 +568,20 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             t.RFB[wd + 1] = (uint32_t)(bal >> 32);
     }
     __syncthreads();
-    const int32_t n_comp = popcount_prefix(t.RFB, t.RFP, (n_runs + 31) >> 5);
+    const int32_t n_comp = popcount_prefix<NT>(t.RFB, t.RFP, (n_runs + 31) >> 5);
     __syncthreads();
-    for (int k = tid; k < n_runs; k += kThreads)
+    for (int k = tid; k < n_runs; k += NT)
         t.RT[k] = (uint16_t)rank_of(t.RFB, t.RFP, t.P[k]);
     __syncthreads();
 
     // 5. canonical key of each component: its first pixel in raster order,
     // the minimum over its nodes of the node's first pixel (top row first)
-    for (int c = tid; c < n_comp; c += kThreads)
+    for (int c = tid; c < n_comp; c += NT)
         t.P[c] = 0x7FFFFFFF;
-    for (int i = tid; i < G::RW; i += kThreads)
+    for (int i = tid; i < G::RW; i += NT)
         t.RFB[i] = 0u;  // from here on: boundary components
     __syncthreads();
-    for (int k = tid; k < n_runs; k += kThreads) {
+    for (int k = tid; k < n_runs; k += NT) {
         const int sp = t.SP[k];
         const int R = sp / TW, col = sp % TW;
         int32_t key;
@@ -597,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
 
     // 6. components touching an edge shared with another tile
     const bool top = ty > 0, bot = ty < im.NTY - 1, left = tx > 0, right = tx < im.NTX - 1;
-    for (int i = tid; i < 2 * NW + 2 * TH; i += kThreads) {
+    for (int i = tid; i < 2 * NW + 2 * TH; i += NT) {
         if (i < 2 * NW) {
             const int side = i / NW, w = i % NW;
             if ((side == 0 && !top) || (side == 1 && !bot))
@@ -624,8 +637,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
         }
     }
     __syncthreads();
-    const int32_t n_bound = popcount_prefix(t.RFB, t.RFP, (n_comp + 31) >> 5);
-    for (int c = tid; c < n_comp; c += kThreads) {
+    const int32_t n_bound = popcount_prefix<NT>(t.RFB, t.RFP, (n_comp + 31) >> 5);
+    for (int c = tid; c < n_comp; c += NT) {
         if (!((t.RFB[c >> 5] >> (c & 31)) & 1u)) {
             const int32_t key = t.P[c];
             atomicOr(&t.RK[key >> 5], 1u << (key & 31));
@@ -636,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
 
     // 7. exports
     const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int c = tid; c < n_comp; c += kThreads) {
+    for (int c = tid; c < n_comp; c += NT) {
         if ((t.RFB[c >> 5] >> (c & 31)) & 1u) {
             const int32_t j = rank_of(t.RFB, t.RFP, c);
             const int32_t key = t.P[c];
@@ -649,7 +662,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
         }
     }
     // edge buffers: boundary index of the component of every edge pixel
-    for (int i = tid; i < 2 * TW + 2 * TH; i += kThreads) {
+    for (int i = tid; i < 2 * TW + 2 * TH; i += NT) {
         int r, c;
         uint16_t *dst;
         bool on;
@@ -673,17 +686,17 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(Batch b) {
             v = (uint16_t)rank_of(t.RFB, t.RFP, t.RT[node_at(t, r / BH, c)]);
         *dst = v;
     }
-    for (int r = tid; r < TH; r += kThreads)
+    for (int r = tid; r < TH; r += NT)
         if (y0 + r < im.H)
             im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.rowcnt[r];
     uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
-    for (int k = tid; k < n_runs; k += kThreads)
+    for (int k = tid; k < n_runs; k += NT)
         grt[k] = t.RT[k];
     uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
-    for (int c = tid; c < n_comp; c += kThreads)
+    for (int c = tid; c < n_comp; c += NT)
         gck[c] = (uint16_t)t.P[c];
     uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
-    for (int i = tid; i < ((n_comp + 31) >> 5); i += kThreads)
+    for (int i = tid; i < ((n_comp + 31) >> 5); i += NT)
         gcb[i] = t.RFB[i];
     if (tid == 0) {
         im.tcnt[ti * 4 + 0] = n_runs;
@@ -888,7 +901,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_blocks(Batch b) {
         sum += v[i];
     }
     int32_t total;
-    int32_t run = block_exclusive_scan(sum, &total);
+    int32_t run = block_exclusive_scan<kThreads>(sum, &total);
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         if (base + i < L)
@@ -906,7 +919,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(Batch b) {
         int i = base + threadIdx.x;
         int32_t v = i < im.nblk ? im.blk[i] : 0;
         int32_t total;
-        int32_t ex = block_exclusive_scan(v, &total);
+        int32_t ex = block_exclusive_scan<kThreads>(v, &total);
         if (i < im.nblk)
             im.blk[i] = carry + ex;
         carry += total;
@@ -955,8 +968,10 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
 };
 
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kThreads) void k_relabel(Batch b) {
+__global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b) {
     using G = Geo<NSR, TW, BH>;
+    constexpr int NT = kTileThreads;
+    constexpr int MPT = (G::NM + NT - 1) / NT;
     constexpr int NW = G::NW, TH = G::TH;
     __shared__ RelabelLds<NSR, TW, BH> t;
     const Img &im = find_img(b, blockIdx.x, kTile);
@@ -968,14 +983,14 @@ __global__ __launch_bounds__(kThreads) void k_relabel(Batch b) {
     const int n_comp = im.tcnt[ti * 4 + 1];
     const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
 #pragma unroll
-    for (int k = 0; k < G::MPT; k++) {
-        const int i = tid + k * kThreads;
+    for (int k = 0; k < MPT; k++) {
+        const int i = tid + k * NT;
         if (i < G::NM) {
             t.M[i] = gmask[i];
             t.RM[i] = 0u;
         }
     }
-    for (int r = tid; r < TH; r += kThreads) {
+    for (int r = tid; r < TH; r += NT) {
         int32_t v = 0;
         if (y0 + r < im.H) {
             const int64_t sg = (int64_t)(y0 + r) * im.NTX + tx;
@@ -985,18 +1000,18 @@ __global__ __launch_bounds__(kThreads) void k_relabel(Batch b) {
     }
     const int ncw = (n_comp + 31) >> 5;
     const uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
-    for (int i = tid; i < ncw; i += kThreads)
+    for (int i = tid; i < ncw; i += NT)
         t.BFB[i] = gcb[i];
     __syncthreads();
-    number_runs<NSR, TW, BH>(t);
-    popcount_prefix(t.BFB, t.BFP, ncw);
+    number_runs<NSR, TW, BH, NT>(t);
+    popcount_prefix<NT>(t.BFB, t.BFP, ncw);
     __syncthreads();
 
     // component labels: boundary components from the merged global sets,
     // interior components ranked inside their row segment
     const uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
     const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int c = tid; c < n_comp; c += kThreads) {
+    for (int c = tid; c < n_comp; c += NT) {
         const int key = gck[c];
         if ((t.BFB[c >> 5] >> (c & 31)) & 1u) {
             const uint32_t id = (uint32_t)(cbase + rank_of(t.BFB, t.BFP, c));
@@ -1012,7 +1027,7 @@ __global__ __launch_bounds__(kThreads) void k_relabel(Batch b) {
         }
     }
     __syncthreads();
-    for (int c = tid; c < n_comp; c += kThreads) {
+    for (int c = tid; c < n_comp; c += NT) {
         const int32_t v = t.CF[c];
         if (v < 0) {
             const int key = ~v, kr = key / TW;
@@ -1021,14 +1036,14 @@ __global__ __launch_bounds__(kThreads) void k_relabel(Batch b) {
     }
     __syncthreads();
     const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
-    for (int k = tid; k < n_runs; k += kThreads)
+    for (int k = tid; k < n_runs; k += NT)
         t.RF[k] = t.CF[grt[k]];
     __syncthreads();
 
     // write: one tile row segment of 256 pixels per wave instruction
     const int wave = tid >> 6, lane = tid & 63;
     const bool vec_ok = ((im.W & 3) == 0) && ((reinterpret_cast<uintptr_t>(im.labels) & 15u) == 0);
-    for (int r = wave; r < TH; r += kThreads / 64) {
+    for (int r = wave; r < TH; r += NT / 64) {
         const int y = y0 + r;
         if (y >= im.H)
             break;
