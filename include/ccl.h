@@ -134,7 +134,7 @@ int ccl_tile_count(void);
  * ccl_profile_read waits for the recorded events and writes the summed
  * milliseconds of each phase over all calls since the previous read into
  * ms[0..nphase) (phases: tile scan, boundary merge, flatten, scan blocks,
- * scan totals, publish, labeling pass), and the number of calls into
+ * scan totals, component labels, labeling pass), and the number of calls into
  * *ncalls (may be NULL).  Used by the benchmark to time single kernels on
  * the stream they run on.
  */

@@ -196,7 +196,7 @@ def release():
     _check(_lib.ccl_release())
 
 
-PHASES = ("tile_scan", "boundary_merge", "flatten", "scan_blocks", "scan_totals", "publish", "labeling_pass")
+PHASES = ("tile_scan", "boundary_merge", "flatten", "scan_blocks", "scan_totals", "component_labels", "labeling_pass")
 
 
 def profile(enable: bool):

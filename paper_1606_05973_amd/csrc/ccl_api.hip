@@ -31,7 +31,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
     int32_t th, NTY, NTX, NT, nblk, nedge, nm, rcap, rw, cap;
-    size_t masks, rt, ck, cb, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
+    size_t masks, rt, ck, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
 Layout layout_of(int64_t H, int64_t W, int conn, const TileCfg &c) {
@@ -58,6 +58,7 @@ Layout layout_of(int64_t H, int64_t W, int conn, const TileCfg &c) {
     L.rt = take(NT * L.rcap * sizeof(uint16_t));
     L.ck = take(NT * L.rcap * sizeof(uint16_t));
     L.cb = take(NT * L.rw * sizeof(uint32_t));
+    L.cf = take(NT * L.rcap * sizeof(int32_t));
     L.tcnt = take(NT * 4 * sizeof(int32_t));
     L.he = take((size_t)L.NTY * 2 * W * sizeof(uint16_t));
     L.ve = take((size_t)L.NTX * 2 * H * sizeof(uint16_t));
@@ -144,6 +145,7 @@ Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     im.rt = reinterpret_cast<uint16_t *>(base + L.rt);
     im.ck = reinterpret_cast<uint16_t *>(base + L.ck);
     im.cb = reinterpret_cast<uint32_t *>(base + L.cb);
+    im.cf = reinterpret_cast<int32_t *>(base + L.cf);
     im.tcnt = reinterpret_cast<int32_t *>(base + L.tcnt);
     im.he = reinterpret_cast<uint16_t *>(base + L.he);
     im.ve = reinterpret_cast<uint16_t *>(base + L.ve);
@@ -227,7 +229,7 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     pm.mark();
     hipLaunchKernelGGL(k_scan_top, dim3((uint32_t)nimg), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_publish<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
     pm.mark();
     hipLaunchKernelGGL((k_relabel<NSR, TW, BH>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     pm.mark();

@@ -51,6 +51,7 @@ struct Img {
     uint16_t *rt;         // [NT][RCAP]  local component of each node
     uint16_t *ck;         // [NT][RCAP]  canonical key (local pixel index) of each local component
     uint32_t *cb;         // [NT][RW]    local component touches a shared tile edge (bit)
+    int32_t *cf;          // [NT][RCAP]  final label of each local component
     int32_t *tcnt;        // [NT][4]     nodes, components, boundary components
     uint16_t *he;         // [NTY][2][W] boundary index of each top(0)/bottom(1) tile-row pixel
     uint16_t *ve;         // [NTX][2][H] same for the left(0)/right(1) tile columns
@@ -388,6 +389,7 @@ struct ScanLds : RunLds<NSR, TW, BH> {
     int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
     uint16_t RT[G::RCAP];   // component ordinal of each node
     uint16_t SP[G::RCAP];   // start of each node: block row * TW + column
+    uint32_t RRB[G::RW];    // node lies in the block row of its root (bit per node)
     uint32_t RFB[G::RW];    // root nodes (bit per node); later boundary components (bit per component)
     int32_t RFP[G::RW];
     uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
@@ -570,8 +572,21 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     __syncthreads();
     const int32_t n_comp = popcount_prefix<NT>(t.RFB, t.RFP, (n_runs + 31) >> 5);
     __syncthreads();
-    for (int k = tid; k < n_runs; k += NT)
-        t.RT[k] = (uint16_t)rank_of(t.RFB, t.RFP, t.P[k]);
+    for (int k0 = 0; k0 < n_runs; k0 += NT) {
+        const int k = k0 + tid;
+        bool same_row = false;
+        if (k < n_runs) {
+            const int32_t root = t.P[k];
+            t.RT[k] = (uint16_t)rank_of(t.RFB, t.RFP, root);
+            same_row = (t.SP[k] / TW) == (t.SP[root] / TW);
+        }
+        const uint64_t bal = __ballot(same_row);
+        const int wd = (k0 + wave * 64) >> 5;
+        if (lane == 0 && wd < G::RW)
+            t.RRB[wd] = (uint32_t)bal;
+        if (lane == 32 && wd + 1 < G::RW)
+            t.RRB[wd + 1] = (uint32_t)(bal >> 32);
+    }
     __syncthreads();
 
     // 5. canonical key of each component: its first pixel in raster order,
@@ -584,6 +599,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     for (int k = tid; k < n_runs; k += NT) {
         const int sp = t.SP[k];
         const int R = sp / TW, col = sp % TW;
+        // the first pixel of a component lies in the block row of its root
+        // (the root is its first node in block-row order)
+        if (!((t.RRB[k >> 5] >> (k & 31)) & 1u))
+            continue;
         int32_t key;
         if (BH == 1) {
             key = sp;
@@ -787,9 +806,11 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     uint32_t cm2 = u2;                                    // partner at c+1 (U2)
     constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
     uint64_t *P = im.uf;
-    // flat loop: one union step per iteration, next contact when one ends
+    // flat loop: one union step per iteration, next contact when one ends;
+    // a contact joining the same two components as the previous one is
+    // skipped (long stretches of one component along an edge)
     bool busy = false;
-    uint32_t rx = 0, ry = 0;
+    uint32_t rx = 0, ry = 0, lastx = 0xFFFFFFFFu, lasty = 0xFFFFFFFFu;
     for (;;) {
         if (!busy) {
             if (!cm1 && !cm2)
@@ -813,6 +834,10 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
                 rx = (uint32_t)(((int64_t)(pa / TH) * im.NTX + later_t) * G::CAP + lo[pa]);
                 ry = (uint32_t)(((int64_t)(pb / TH) * im.NTX + earlier_t) * G::CAP + hi[pb]);
             }
+            if (rx == lastx && ry == lasty)
+                continue;
+            lastx = rx;
+            lasty = ry;
             busy = true;
         }
         const uint64_t px = aload<AG>(P + rx);
@@ -862,15 +887,29 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
         rowc[r] = 0;
     __syncthreads();
     const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int j = tid; j < n; j += kThreads) {
+    // flat loop: every lane walks its components' parent chains one load per
+    // iteration, without waiting for other lanes' longer chains; the walk's
+    // end (the root entry) is written back to the component's own entry
+    int j = tid;
+    uint32_t r = (uint32_t)(cbase + j);
+    while (j < n) {
+        const uint64_t v = aload<__HIP_MEMORY_SCOPE_AGENT>(im.uf + r);
+        if ((uint32_t)v != r) {
+            r = (uint32_t)v;
+            continue;
+        }
         const uint32_t id = (uint32_t)(cbase + j);
-        const bool is = find_compress_global(im.uf, id) == id;
+        const bool is = r == id;
+        if (!is)
+            astore<__HIP_MEMORY_SCOPE_AGENT>(im.uf + id, v);
         im.broot[id] = is;
         if (is) {
             const int key = im.bkey[id];
             atomicOr(&RK[key >> 5], 1u << (key & 31));
             atomicAdd(&rowc[key / TW], 1);
         }
+        j += kThreads;
+        r = (uint32_t)(cbase + j);
     }
     __syncthreads();
     for (int j = tid; j < n; j += kThreads) {
@@ -929,50 +968,90 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(Batch b) {
 }
 
 // ------------------------------------------------------------------------
-// K3b: final label of every root boundary component: 1 + roots before its
-// segment + its offset inside the segment.
+// K4c: final label of every local component of a tile, stored in its table.
+//   label(root of a set) = 1 + roots before its row segment + its offset
+//   inside the segment (both known after K3a and K4), computable from any
+//   tile, so a non-root boundary component reads its root's entries
+//   directly; interior components are ranked inside their row segment
+//   among the segment's roots (interior and boundary).
 // ------------------------------------------------------------------------
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kThreads) void k_publish(Batch b) {
+__device__ __forceinline__ int32_t segment_base(const Img &im, int tile, int key) {
+    constexpr int TH = Geo<NSR, TW, BH>::TH;
+    const int ty = tile / im.NTX, tx = tile % im.NTX;
+    const int64_t sg = (int64_t)(ty * TH + key / TW) * im.NTX + tx;
+    return im.seg[sg] + im.blk[sg / kScanChunk];
+}
+
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
     using G = Geo<NSR, TW, BH>;
-    constexpr int TH = G::TH;
+    constexpr int NW = G::NW, TH = G::TH;
+    __shared__ uint32_t BFB[G::RW];
+    __shared__ int32_t BFP[G::RW];
+    __shared__ uint32_t RM[G::NM];   // keys of the segment roots (bit per pixel)
+    __shared__ int32_t rowbase[TH];
     const Img &im = find_img(b, blockIdx.x, kTile);
     const int ti = blockIdx.x - im.tile0;
-    const int n = im.tcnt[ti * 4 + 2];
-    const int ty = ti / im.NTX, tx = ti % im.NTX;
+    const int ty = ti / im.NTX;
+    const int y0 = ty * TH;
+    const int tid = threadIdx.x;
+    const int n_comp = im.tcnt[ti * 4 + 1];
+    const int ncw = (n_comp + 31) >> 5;
+    const uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
+    for (int i = tid; i < ncw; i += kThreads)
+        BFB[i] = gcb[i];
+    for (int i = tid; i < G::NM; i += kThreads)
+        RM[i] = 0u;
+    for (int r = tid; r < TH; r += kThreads)
+        rowbase[r] = (y0 + r < im.H) ? segment_base<NSR, TW, BH>(im, ti, r * TW) : 0;
+    __syncthreads();
+    popcount_prefix<kThreads>(BFB, BFP, ncw);
+    const uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
+    int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
     const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-        const uint32_t id = (uint32_t)(cbase + j);
-        if (!im.broot[id])
-            continue;
-        const int key = im.bkey[id];
-        const int64_t sg = (int64_t)(ty * TH + key / TW) * im.NTX + tx;
-        im.bval[id] = 1 + im.seg[sg] + im.blk[sg / kScanChunk] + im.bval[id];
+    for (int c = tid; c < n_comp; c += kThreads) {
+        const int key = gck[c];
+        if ((BFB[c >> 5] >> (c & 31)) & 1u) {
+            const uint32_t id = (uint32_t)(cbase + rank_of(BFB, BFP, c));
+            if (im.broot[id]) {
+                gcf[c] = 1 + rowbase[key / TW] + im.bval[id];
+                atomicOr(&RM[key >> 5], 1u << (key & 31));
+            } else {
+                const uint32_t rid = (uint32_t)im.uf[id];
+                gcf[c] = 1 + segment_base<NSR, TW, BH>(im, (int)(rid / G::CAP), im.bkey[rid]) + im.bval[rid];
+            }
+        } else {
+            atomicOr(&RM[key >> 5], 1u << (key & 31));
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < n_comp; c += kThreads) {
+        if (!((BFB[c >> 5] >> (c & 31)) & 1u)) {
+            const int key = gck[c], kr = key / TW;
+            gcf[c] = 1 + rowbase[kr] + popc_before(&RM[kr * NW], key % TW);
+        }
     }
 }
 
 // ------------------------------------------------------------------------
 // K5: labeling pass.  Rebuild the node numbering from the stored bitmask,
-// give every local component its final label, write all pixels with
+// look every pixel's label up through its node and component, write all pixels with
 // 16-byte stores.
 // ------------------------------------------------------------------------
 template <int NSR, int TW, int BH>
 struct RelabelLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
+    uint16_t RT[G::RCAP];   // local component of each node
     int32_t CF[G::RCAP];    // final label of each local component
-    int32_t RF[G::RCAP];    // final label of each node
-    uint32_t RM[G::NM];     // keys of components that are global roots (bit per pixel)
-    uint32_t BFB[G::RW];
-    int32_t BFP[G::RW];
-    int32_t rowbase[G::TH];
 };
 
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b) {
     using G = Geo<NSR, TW, BH>;
+    constexpr int NW = G::NW, TH = G::TH;
     constexpr int NT = kTileThreads;
     constexpr int MPT = (G::NM + NT - 1) / NT;
-    constexpr int NW = G::NW, TH = G::TH;
     __shared__ RelabelLds<NSR, TW, BH> t;
     const Img &im = find_img(b, blockIdx.x, kTile);
     const int ti = blockIdx.x - im.tile0;
@@ -980,64 +1059,22 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b) {
     const int y0 = ty * TH, x0 = tx * TW;
     const int tid = threadIdx.x;
     const int n_runs = im.tcnt[ti * 4 + 0];
-    const int n_comp = im.tcnt[ti * 4 + 1];
     const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
 #pragma unroll
     for (int k = 0; k < MPT; k++) {
         const int i = tid + k * NT;
-        if (i < G::NM) {
+        if (i < G::NM)
             t.M[i] = gmask[i];
-            t.RM[i] = 0u;
-        }
     }
-    for (int r = tid; r < TH; r += NT) {
-        int32_t v = 0;
-        if (y0 + r < im.H) {
-            const int64_t sg = (int64_t)(y0 + r) * im.NTX + tx;
-            v = im.seg[sg] + im.blk[sg / kScanChunk];
-        }
-        t.rowbase[r] = v;
-    }
-    const int ncw = (n_comp + 31) >> 5;
-    const uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
-    for (int i = tid; i < ncw; i += NT)
-        t.BFB[i] = gcb[i];
+    const int n_comp = im.tcnt[ti * 4 + 1];
+    const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
+    const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+    for (int k = tid; k < n_runs; k += NT)
+        t.RT[k] = grt[k];
+    for (int c = tid; c < n_comp; c += NT)
+        t.CF[c] = gcf[c];
     __syncthreads();
     number_runs<NSR, TW, BH, NT>(t);
-    popcount_prefix<NT>(t.BFB, t.BFP, ncw);
-    __syncthreads();
-
-    // component labels: boundary components from the merged global sets,
-    // interior components ranked inside their row segment
-    const uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
-    const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int c = tid; c < n_comp; c += NT) {
-        const int key = gck[c];
-        if ((t.BFB[c >> 5] >> (c & 31)) & 1u) {
-            const uint32_t id = (uint32_t)(cbase + rank_of(t.BFB, t.BFP, c));
-            if (im.broot[id]) {
-                t.CF[c] = im.bval[id];
-                atomicOr(&t.RM[key >> 5], 1u << (key & 31));
-            } else {
-                t.CF[c] = im.bval[(uint32_t)im.uf[id]];
-            }
-        } else {
-            atomicOr(&t.RM[key >> 5], 1u << (key & 31));
-            t.CF[c] = ~key;
-        }
-    }
-    __syncthreads();
-    for (int c = tid; c < n_comp; c += NT) {
-        const int32_t v = t.CF[c];
-        if (v < 0) {
-            const int key = ~v, kr = key / TW;
-            t.CF[c] = 1 + t.rowbase[kr] + popc_before(&t.RM[kr * NW], key % TW);
-        }
-    }
-    __syncthreads();
-    const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
-    for (int k = tid; k < n_runs; k += NT)
-        t.RF[k] = t.CF[grt[k]];
     __syncthreads();
 
     // write: one tile row segment of 256 pixels per wave instruction
@@ -1057,10 +1094,10 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b) {
             const uint32_t s = t.S[R * NW + w];
             const int32_t bs = t.base[R * NW + w] - 1;
             i32x4 o;
-            o.x = (m & 1u) ? t.RF[bs + __popc(s & mask_le(b0))] : 0;
-            o.y = (m & 2u) ? t.RF[bs + __popc(s & mask_le(b0 + 1))] : 0;
-            o.z = (m & 4u) ? t.RF[bs + __popc(s & mask_le(b0 + 2))] : 0;
-            o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
+            o.x = (m & 1u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0))]] : 0;
+            o.y = (m & 2u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0 + 1))]] : 0;
+            o.z = (m & 4u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0 + 2))]] : 0;
+            o.w = (m & 8u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0 + 3))]] : 0;
             int32_t *dst = im.labels + (int64_t)y * im.W + x;
             if (vec_ok && x + 4 <= im.W) {
                 __builtin_nontemporal_store(o, reinterpret_cast<i32x4 *>(dst));
