@@ -211,6 +211,23 @@ struct PhaseMarks {
     }
 };
 
+// Workgroups of a persistent launch of `kernel`: as many as can be resident
+// at once (occupancy x CUs), computed once per kernel.
+template <class K>
+int persistent_groups(K kernel, int threads) {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+            per_cu = 1;
+        n = cus * per_cu;
+    }
+    return n;
+}
+
 template <int NSR, int TW, int BH>
 int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg, hipStream_t s) {
     if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
@@ -231,7 +248,9 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     pm.mark();
     hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_relabel<NSR, TW, BH>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
+    hipLaunchKernelGGL((k_relabel<NSR, TW, BH>),
+                       dim3((uint32_t)std::min<int64_t>(tiles, persistent_groups(k_relabel<NSR, TW, BH>, kTileThreads))),
+                       dim3(kTileThreads), 0, s, b, (int32_t)tiles);
     pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }

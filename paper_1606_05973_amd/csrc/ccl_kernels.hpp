@@ -1044,74 +1044,112 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
     uint16_t RT[G::RCAP];   // local component of each node
     int32_t CF[G::RCAP];    // final label of each local component
+    int32_t RF[G::RCAP];    // final label of each node
 };
 
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b) {
+__global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr int NW = G::NW, TH = G::TH;
     constexpr int NT = kTileThreads;
     constexpr int MPT = (G::NM + NT - 1) / NT;
+    constexpr int TPT = (G::RCAP + NT - 1) / NT;  // table entries per thread
     __shared__ RelabelLds<NSR, TW, BH> t;
-    const Img &im = find_img(b, blockIdx.x, kTile);
-    const int ti = blockIdx.x - im.tile0;
-    const int ty = ti / im.NTX, tx = ti % im.NTX;
-    const int y0 = ty * TH, x0 = tx * TW;
     const int tid = threadIdx.x;
-    const int n_runs = im.tcnt[ti * 4 + 0];
-    const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
-#pragma unroll
-    for (int k = 0; k < MPT; k++) {
-        const int i = tid + k * NT;
-        if (i < G::NM)
-            t.M[i] = gmask[i];
-    }
-    const int n_comp = im.tcnt[ti * 4 + 1];
-    const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
-    const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
-    for (int k = tid; k < n_runs; k += NT)
-        t.RT[k] = grt[k];
-    for (int c = tid; c < n_comp; c += NT)
-        t.CF[c] = gcf[c];
-    __syncthreads();
-    number_runs<NSR, TW, BH, NT>(t);
-    __syncthreads();
-
-    // write: one tile row segment of 256 pixels per wave instruction
     const int wave = tid >> 6, lane = tid & 63;
-    const bool vec_ok = ((im.W & 3) == 0) && ((reinterpret_cast<uintptr_t>(im.labels) & 15u) == 0);
-    for (int r = wave; r < TH; r += NT / 64) {
-        const int y = y0 + r;
-        if (y >= im.H)
-            break;
-        const int R = r / BH;
-        for (int q = lane; q < TW / 4; q += 64) {
-            const int c0 = q * 4, x = x0 + c0;
-            if (x >= im.W)
-                continue;
-            const int w = c0 >> 5, b0 = c0 & 31;
-            const uint32_t m = t.M[r * NW + w] >> b0;
-            const uint32_t s = t.S[R * NW + w];
-            const int32_t bs = t.base[R * NW + w] - 1;
-            i32x4 o;
-            o.x = (m & 1u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0))]] : 0;
-            o.y = (m & 2u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0 + 1))]] : 0;
-            o.z = (m & 4u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0 + 2))]] : 0;
-            o.w = (m & 8u) ? t.CF[t.RT[bs + __popc(s & mask_le(b0 + 3))]] : 0;
-            int32_t *dst = im.labels + (int64_t)y * im.W + x;
-            if (vec_ok && x + 4 <= im.W) {
-                __builtin_nontemporal_store(o, reinterpret_cast<i32x4 *>(dst));
-            } else {
-                const int nn = im.W - x < 4 ? im.W - x : 4;
-                dst[0] = o.x;
-                if (nn > 1)
-                    dst[1] = o.y;
-                if (nn > 2)
-                    dst[2] = o.z;
-                if (nn > 3)
-                    dst[3] = o.w;
+    // Persistent: each workgroup walks tiles blockIdx.x, +gridDim.x, ...
+    // While a tile's stores drain, the next tile's mask and tables are
+    // already in flight into registers.
+    uint32_t pm[MPT];
+    uint32_t prt[TPT];
+    int32_t pcf[TPT];
+    int pn_runs = 0, pn_comp = 0;
+    auto fetch = [&](int tile) {
+        const Img &im = find_img(b, tile, kTile);
+        const int ti = tile - im.tile0;
+        pn_runs = im.tcnt[ti * 4 + 0];
+        pn_comp = im.tcnt[ti * 4 + 1];
+        const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+#pragma unroll
+        for (int k = 0; k < MPT; k++) {
+            const int i = tid + k * NT;
+            pm[k] = i < G::NM ? gmask[i] : 0u;
+        }
+        const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
+        const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+#pragma unroll
+        for (int k = 0; k < TPT; k++) {
+            const int i = tid + k * NT;
+            prt[k] = i < pn_runs ? grt[i] : 0u;
+            pcf[k] = i < pn_comp ? gcf[i] : 0;
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles)
+        fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const Img &im = find_img(b, tile, kTile);
+        const int ti = tile - im.tile0;
+        const int ty = ti / im.NTX, tx = ti % im.NTX;
+        const int y0 = ty * TH, x0 = tx * TW;
+#pragma unroll
+        for (int k = 0; k < MPT; k++) {
+            const int i = tid + k * NT;
+            if (i < G::NM)
+                t.M[i] = pm[k];
+        }
+#pragma unroll
+        for (int k = 0; k < TPT; k++) {
+            const int i = tid + k * NT;
+            if (i < pn_runs)
+                t.RT[i] = (uint16_t)prt[k];
+            if (i < pn_comp)
+                t.CF[i] = pcf[k];
+        }
+        __syncthreads();
+        number_runs<NSR, TW, BH, NT>(t);
+        for (int k = tid; k < pn_runs; k += NT)
+            t.RF[k] = t.CF[t.RT[k]];
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles)
+            fetch(tile + gridDim.x);
+
+        // write: one tile row segment of 256 pixels per wave instruction
+        const bool vec_ok = ((im.W & 3) == 0) && ((reinterpret_cast<uintptr_t>(im.labels) & 15u) == 0);
+        for (int r = wave; r < TH; r += NT / 64) {
+            const int y = y0 + r;
+            if (y >= im.H)
+                break;
+            const int R = r / BH;
+            for (int q = lane; q < TW / 4; q += 64) {
+                const int c0 = q * 4, x = x0 + c0;
+                if (x >= im.W)
+                    continue;
+                const int w = c0 >> 5, b0 = c0 & 31;
+                const uint32_t m = t.M[r * NW + w] >> b0;
+                const uint32_t s = t.S[R * NW + w];
+                const int32_t bs = t.base[R * NW + w] - 1;
+                i32x4 o;
+                o.x = (m & 1u) ? t.RF[bs + __popc(s & mask_le(b0))] : 0;
+                o.y = (m & 2u) ? t.RF[bs + __popc(s & mask_le(b0 + 1))] : 0;
+                o.z = (m & 4u) ? t.RF[bs + __popc(s & mask_le(b0 + 2))] : 0;
+                o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
+                int32_t *dst = im.labels + (int64_t)y * im.W + x;
+                if (vec_ok && x + 4 <= im.W) {
+                    __builtin_nontemporal_store(o, reinterpret_cast<i32x4 *>(dst));
+                } else {
+                    const int nn = im.W - x < 4 ? im.W - x : 4;
+                    dst[0] = o.x;
+                    if (nn > 1)
+                        dst[1] = o.y;
+                    if (nn > 2)
+                        dst[2] = o.z;
+                    if (nn > 3)
+                        dst[3] = o.w;
+                }
             }
         }
+        __syncthreads();
     }
 }
 
