@@ -65,6 +65,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=21568, help="image side (square)")
     ap.add_argument("--p", type=float, default=0.5, help="Bernoulli foreground probability")
+    ap.add_argument("--content", choices=["bernoulli", "grf"], default="bernoulli")
+    ap.add_argument("--sigma", type=float, default=8.0, help="GRF smoothing (px) when --content grf")
+    ap.add_argument("--q", type=float, default=0.5, help="GRF threshold quantile when --content grf")
+    ap.add_argument("--pitch", type=int, default=0,
+                    help="image row pitch in bytes (0 = W); e.g. 256 rounds rows up to 256-byte alignment")
     ap.add_argument("--conn", type=int, default=8)
     ap.add_argument("--tile", type=int, default=0, help="tile configuration id (0 = default)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for cpu_baseline (0 = skip)")
@@ -85,7 +90,13 @@ def main():
 
     dev = torch.device("cuda:0")
     S = args.size
-    img = inputs.bernoulli(S, S, args.p, seed=0, device=dev)
+    stride = S if args.pitch <= 0 else (S + args.pitch - 1) // args.pitch * args.pitch
+    if args.content == "grf":
+        img = inputs.grf(S, S, args.sigma, args.q, seed=0, device=dev, stride=stride)
+        content = f"thresholded Gaussian random field sigma={args.sigma} q={args.q} seed 0"
+    else:
+        img = inputs.bernoulli(S, S, args.p, seed=0, device=dev, stride=stride)
+        content = f"Bernoulli p={args.p} seed 0"
     out = torch.empty((S, S), dtype=torch.int32, device=dev)
     kdev = torch.zeros(1, dtype=torch.int32, device=dev)
     ccl.reserve(ccl.workspace_bytes(S, S, args.conn, args.tile))
@@ -125,7 +136,8 @@ def main():
     dom_ms = phase_ms[dom]
     alg_bytes = PHASE_BYTES_PER_PX[dom] * px
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
-    workload_key = f"bernoulli{args.p}_{S}x{S}_conn{args.conn}_tile{th}x{tw}"
+    workload_key = (f"bernoulli{args.p}" if args.content == "bernoulli" else f"grf{args.sigma}_{args.q}") + \
+        f"_{S}x{S}_conn{args.conn}_tile{th}x{tw}" + (f"_pitch{stride}" if stride != S else "")
     traffic = load_traffic(dom, workload_key)
 
     record = {
@@ -142,9 +154,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": f"{S}x{S} uint8 Bernoulli p={args.p} seed 0, {args.conn}-connectivity, "
-                        "canonical int32 labels",
-            "H": S, "W": S, "conn": args.conn, "tile": [th, tw], "parallelism": "single GPU",
+            "workload": f"{S}x{S} uint8 {content}, {args.conn}-connectivity, canonical int32 labels",
+            "H": S, "W": S, "stride": stride, "conn": args.conn, "tile": [th, tw], "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
@@ -167,7 +178,7 @@ def main():
         import numpy as np
 
         import oracle
-        host = img.cpu().numpy()
+        host = img.cpu().numpy()  # H x W view (row pitch dropped on copy)
         times, ref = [], None
         for _ in range(max(args.cpu_runs, 1)):
             t = time.perf_counter()

@@ -102,6 +102,23 @@ typedef struct {
  */
 int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t stream);
 
+/*
+ * Captured batches.  ccl_batch_graph_create labels nothing: it gives the
+ * batch its own workspace and device descriptor table (uploaded before
+ * capture), captures every launch of ccl_label_batch for these descriptors
+ * into a HIP graph and instantiates it.  ccl_graph_launch replays the whole
+ * batch on `stream` with one graph launch; the image and label buffers named
+ * in the descriptors are the ones used on every replay (refill the images
+ * between replays to label new content of the same shapes).  The graph holds
+ * kernel nodes only.  ccl_graph_destroy synchronises the device and frees
+ * the graph and its workspace.  Errors as for ccl_label_batch, plus
+ * CCL_ERR_NOMEM if the graph's workspace cannot be allocated.
+ */
+typedef struct ccl_graph ccl_graph;
+int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_graph **graph);
+int ccl_graph_launch(ccl_graph *graph, hipStream_t stream);
+int ccl_graph_destroy(ccl_graph *graph);
+
 /* Workspace bytes one ccl_label_ex call needs for an H x W image with the
  * given tile configuration (0 = default); 0 for invalid arguments.  Used for
  * admission by HBM footprint: footprint = image + labels + workspace. */

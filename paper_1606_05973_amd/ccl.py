@@ -49,6 +49,13 @@ _lib.ccl_tile_config.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), cty
 _lib.ccl_tile_config.restype = ctypes.c_int
 _lib.ccl_tile_count.argtypes = []
 _lib.ccl_tile_count.restype = ctypes.c_int
+_lib.ccl_batch_graph_create.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+_lib.ccl_batch_graph_create.restype = ctypes.c_int
+_lib.ccl_graph_launch.argtypes = [ctypes.c_void_p, _stream]
+_lib.ccl_graph_launch.restype = ctypes.c_int
+_lib.ccl_graph_destroy.argtypes = [ctypes.c_void_p]
+_lib.ccl_graph_destroy.restype = ctypes.c_int
 _lib.ccl_profile.argtypes = [ctypes.c_int]
 _lib.ccl_profile.restype = ctypes.c_int
 _lib.ccl_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -171,6 +178,39 @@ def tile_shape(tile: int, conn: int):
     """(tile height, tile width) in pixels of configuration `tile` for `conn`."""
     nsr, tw = tile_configs()[max(tile, 1) - 1]
     return nsr * (2 if conn == 8 else 1), tw
+
+
+class BatchGraph:
+    """A batch captured once into a HIP graph (ccl_batch_graph_create) and
+    replayed with one launch.  The image and label tensors are kept alive and
+    reused on every replay."""
+
+    def __init__(self, imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None):
+        n = len(imgs)
+        conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
+        if outs is None:
+            outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
+        counts = [num_components[i:i + 1] for i in range(n)] if num_components is not None else None
+        self.imgs, self.outs, self.counts = list(imgs), outs, num_components
+        arr = _descs(imgs, conns, outs, counts)
+        h = ctypes.c_void_p()
+        _check(_lib.ccl_batch_graph_create(arr, n, int(tile), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_lib.ccl_graph_launch(self._h, _stream_handle(stream)))
+        return self.outs
+
+    def close(self):
+        if self._h:
+            _check(_lib.ccl_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0) -> int:

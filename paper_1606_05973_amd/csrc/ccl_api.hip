@@ -31,7 +31,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
     int32_t th, NTY, NTX, NT, nblk, nedge, nm, rcap, rw, cap;
-    size_t masks, rt, ck, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
+    size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
 Layout layout_of(int64_t H, int64_t W, int conn, const TileCfg &c) {
@@ -56,7 +56,6 @@ Layout layout_of(int64_t H, int64_t W, int conn, const TileCfg &c) {
     };
     L.masks = take(NT * L.nm * sizeof(uint32_t));
     L.rt = take(NT * L.rcap * sizeof(uint16_t));
-    L.ck = take(NT * L.rcap * sizeof(uint16_t));
     L.cb = take(NT * L.rw * sizeof(uint32_t));
     L.cf = take(NT * L.rcap * sizeof(int32_t));
     L.tcnt = take(NT * 4 * sizeof(int32_t));
@@ -143,7 +142,6 @@ Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     im.ncomp = d.num_components;
     im.masks = reinterpret_cast<uint32_t *>(base + L.masks);
     im.rt = reinterpret_cast<uint16_t *>(base + L.rt);
-    im.ck = reinterpret_cast<uint16_t *>(base + L.ck);
     im.cb = reinterpret_cast<uint32_t *>(base + L.cb);
     im.cf = reinterpret_cast<int32_t *>(base + L.cf);
     im.tcnt = reinterpret_cast<int32_t *>(base + L.tcnt);
@@ -190,8 +188,13 @@ struct PhaseMarks {
     hipStream_t s;
     bool on;
     explicit PhaseMarks(hipStream_t st) : s(st) {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        on = g_prof_on;
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            on = g_prof_on;
+        }
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (on && (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone))
+            on = false;  // no event nodes inside captured graphs
     }
     void mark() {
         if (!on)
@@ -276,7 +279,7 @@ int dispatch(const TileCfg &c, int bh, const Batch &b, int64_t tiles, int64_t ed
 // Workspace: [tables of both groups][per-image regions].
 int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
               const std::vector<size_t> &offs, char *base, Img *dtab, int bh, const TileCfg &c,
-              hipStream_t stream) {
+              hipStream_t stream, bool table_ready = false) {
     const int n = (int)idx.size();
     if (n == 0)
         return CCL_OK;
@@ -300,7 +303,8 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
         b.one = tab[0];
         b.tab = nullptr;
     } else {
-        if (hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
+        if (!table_ready &&
+            hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
             return CCL_ERR_HIP;
         b.tab = dtab;
     }
@@ -340,8 +344,36 @@ int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t 
     return run_group(descs, g4, lays, offs, base, dtab + g8.size(), 1, c, stream);
 }
 
+// Device table of one group, uploaded synchronously (used before capture).
+int upload_group_table(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+                       const std::vector<size_t> &offs, char *base, Img *dtab) {
+    const int n = (int)idx.size();
+    if (n <= 1)
+        return CCL_OK;
+    std::vector<Img> tab(n);
+    int64_t tiles = 0, edges = 0, blocks = 0;
+    for (int k = 0; k < n; k++) {
+        const int i = idx[k];
+        tab[k] = make_img(descs[i], lays[i], base + offs[i]);
+        tab[k].tile0 = (int32_t)tiles;
+        tab[k].edge0 = (int32_t)edges;
+        tab[k].scan0 = (int32_t)blocks;
+        tiles += lays[i].NT;
+        edges += lays[i].nedge;
+        blocks += lays[i].nblk;
+    }
+    return hipMemcpy(dtab, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice) == hipSuccess ? CCL_OK
+                                                                                                     : CCL_ERR_HIP;
+}
+
 }  // namespace
 }  // namespace ccl
+
+struct ccl_graph {
+    void *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 using namespace ccl;
 
@@ -403,6 +435,87 @@ size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile) {
             return 0;
     }
     return batch_bytes(descs, n, c, nullptr, nullptr);
+}
+
+int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_graph **out) {
+    if (!out)
+        return CCL_ERR_NULL;
+    *out = nullptr;
+    if (n <= 0 || !descs)
+        return CCL_ERR_BATCH;
+    TileCfg c;
+    int st = resolve_tile(tile, &c);
+    if (st != CCL_OK)
+        return st;
+    for (int i = 0; i < n; i++) {
+        st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
+        if (st != CCL_OK)
+            return st;
+    }
+    std::vector<Layout> lays;
+    std::vector<size_t> offs;
+    const size_t total = batch_bytes(descs, n, c, &lays, &offs);
+    ccl_graph *g = new ccl_graph();
+    if (hipMalloc(&g->ws, total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete g;
+        return CCL_ERR_NOMEM;
+    }
+    char *base = static_cast<char *>(g->ws);
+    std::vector<int> g8, g4;
+    for (int i = 0; i < n; i++)
+        (descs[i].conn == 8 ? g8 : g4).push_back(i);
+    Img *dtab = reinterpret_cast<Img *>(base);
+    st = upload_group_table(descs, g8, lays, offs, base, dtab);
+    if (st == CCL_OK)
+        st = upload_group_table(descs, g4, lays, offs, base, dtab + g8.size());
+    hipStream_t cs = nullptr;
+    if (st == CCL_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        st = CCL_ERR_HIP;
+    if (st == CCL_OK) {
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            st = CCL_ERR_HIP;
+        } else {
+            int s1 = run_group(descs, g8, lays, offs, base, dtab, 2, c, cs, true);
+            int s2 = s1 == CCL_OK ? run_group(descs, g4, lays, offs, base, dtab + g8.size(), 1, c, cs, true) : s1;
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &graph);
+            st = s2 != CCL_OK ? s2 : (e == hipSuccess ? CCL_OK : CCL_ERR_HIP);
+            g->graph = graph;
+            if (st == CCL_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                st = CCL_ERR_HIP;
+        }
+    }
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (st != CCL_OK) {
+        ccl_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return CCL_OK;
+}
+
+int ccl_graph_launch(ccl_graph *g, hipStream_t stream) {
+    if (!g || !g->exec)
+        return CCL_ERR_NULL;
+    return hipGraphLaunch(g->exec, stream) == hipSuccess ? CCL_OK : CCL_ERR_HIP;
+}
+
+int ccl_graph_destroy(ccl_graph *g) {
+    if (!g)
+        return CCL_OK;
+    int st = CCL_OK;
+    if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess)
+        st = CCL_ERR_HIP;
+    if (g->graph && hipGraphDestroy(g->graph) != hipSuccess)
+        st = CCL_ERR_HIP;
+    if (g->ws) {
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(g->ws) != hipSuccess)
+            st = CCL_ERR_HIP;
+    }
+    delete g;
+    return st;
 }
 
 int ccl_reserve(size_t bytes, hipStream_t stream) {

@@ -49,9 +49,9 @@ struct Img {
     int32_t *ncomp;       // optional K output (device)
     uint32_t *masks;      // [NT][NM]    foreground bitmask of each tile
     uint16_t *rt;         // [NT][RCAP]  local component of each node
-    uint16_t *ck;         // [NT][RCAP]  canonical key (local pixel index) of each local component
     uint32_t *cb;         // [NT][RW]    local component touches a shared tile edge (bit)
-    int32_t *cf;          // [NT][RCAP]  final label of each local component
+    int32_t *cf;          // [NT][RCAP]  canonical key (local pixel index) of each local component,
+                          //             replaced by its final label by the component-label kernel
     int32_t *tcnt;        // [NT][4]     nodes, components, boundary components
     uint16_t *he;         // [NTY][2][W] boundary index of each top(0)/bottom(1) tile-row pixel
     uint16_t *ve;         // [NTX][2][H] same for the left(0)/right(1) tile columns
@@ -711,9 +711,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
     for (int k = tid; k < n_runs; k += NT)
         grt[k] = t.RT[k];
-    uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
+    int32_t *gck = im.cf + (int64_t)ti * G::RCAP;
     for (int c = tid; c < n_comp; c += NT)
-        gck[c] = (uint16_t)t.P[c];
+        gck[c] = t.P[c];
     uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
     for (int i = tid; i < ((n_comp + 31) >> 5); i += NT)
         gcb[i] = t.RFB[i];
@@ -1007,8 +1007,9 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
         rowbase[r] = (y0 + r < im.H) ? segment_base<NSR, TW, BH>(im, ti, r * TW) : 0;
     __syncthreads();
     popcount_prefix<kThreads>(BFB, BFP, ncw);
-    const uint16_t *gck = im.ck + (int64_t)ti * G::RCAP;
+    // each slot holds the component's key until this kernel writes its label
     int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+    const int32_t *gck = gcf;
     const int64_t cbase = (int64_t)ti * G::CAP;
     for (int c = tid; c < n_comp; c += kThreads) {
         const int key = gck[c];

@@ -24,7 +24,8 @@ def test_header_declares_api():
     names = _declared_functions()
     for expected in ("ccl_label", "ccl_label_ex", "ccl_label_batch", "ccl_workspace_bytes",
                      "ccl_batch_workspace_bytes", "ccl_reserve", "ccl_release", "ccl_tile_config",
-                     "ccl_tile_count", "ccl_strerror"):
+                     "ccl_tile_count", "ccl_strerror", "ccl_batch_graph_create", "ccl_graph_launch",
+                     "ccl_graph_destroy", "ccl_profile", "ccl_profile_read"):
         assert expected in names
 
 
@@ -59,6 +60,12 @@ def test_status_codes_on_host():
         arr[i].conn = 8
     arr[1].conn = 5
     assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_CONN"]
+    # graph creation validates the same way before allocating anything
+    h = ctypes.c_void_p()
+    assert lib.ccl_batch_graph_create(arr, 2, 0, ctypes.byref(h)) == S["CCL_ERR_CONN"] and not h.value
+    assert lib.ccl_batch_graph_create(arr, 0, 0, ctypes.byref(h)) == S["CCL_ERR_BATCH"]
+    assert lib.ccl_graph_launch(None, None) == S["CCL_ERR_NULL"]
+    assert lib.ccl_graph_destroy(None) == 0
 
 
 def test_strerror_and_tiles():
@@ -80,9 +87,10 @@ def test_workspace_bytes():
     a = ccl.workspace_bytes(1000, 1000)
     b = ccl.workspace_bytes(2000, 2000)
     assert 0 < a < b
-    # worst-case per-tile capacities: below the int32 labels' own size
+    # worst-case per-tile capacities (every pixel its own component under
+    # 4-conn): a few bytes per pixel, reported for admission by HBM footprint
     assert ccl.workspace_bytes(21568, 21568) < 4 * 21568 * 21568
-    assert ccl.workspace_bytes(21568, 21568, conn=4) < 4 * 21568 * 21568
+    assert ccl.workspace_bytes(21568, 21568, conn=4) < 5 * 21568 * 21568
     both = ccl.batch_workspace_bytes([(1000, 1000), (2000, 2000)])
     assert both >= a + b - 1024
 

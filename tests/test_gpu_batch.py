@@ -1,0 +1,108 @@
+"""Batched, captured and served forms on the GPU, bit-exact against the
+oracle and against the single-image path."""
+import random
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1606_05973_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ccl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1606_05973_amd import ccl as mod
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _oracle(img, conn):
+    return oracle.cclremsp(img.cpu().numpy(), conn)
+
+
+def test_batch_graph_replays(ccl):
+    specs = inputs.batch_specs(12, seed=31, max_side=600)
+    imgs = [inputs.make(s, device=DEV) for s in specs]
+    conns = [8 if i % 2 else 4 for i in range(len(imgs))]
+    k = torch.full((len(imgs),), -1, dtype=torch.int32, device=DEV)
+    say("case graph create n=12")
+    g = ccl.BatchGraph(imgs, conns, num_components=k)
+    other = inputs.bernoulli(300, 300, 0.5, seed=5, device=DEV)
+    try:
+        for rep in range(4):
+            # new content in the same buffers, eager work between replays
+            for i, (img, s) in enumerate(zip(imgs, specs)):
+                img.copy_(inputs.bernoulli(s["H"], s["W"], 0.2 + 0.15 * ((rep + i) % 4), seed=rep * 100 + i,
+                                           device=DEV))
+            eager = ccl.label(other, 8)
+            torch.cuda.synchronize()
+            say(f"case graph replay {rep}")
+            outs = g.launch()
+            torch.cuda.synchronize()
+            for i, img in enumerate(imgs):
+                ref, kref = _oracle(img, conns[i])
+                assert np.array_equal(outs[i].cpu().numpy(), ref), (rep, i)
+                assert int(k[i].item()) == kref
+            assert torch.equal(eager, ccl.label(other, 8))
+    finally:
+        g.close()
+
+
+def test_autotuner_picks_and_caches(ccl, tmp_path):
+    from paper_1606_05973_amd import autotune
+    t = autotune.Autotuner(str(tmp_path / "tiles.json"))
+    say("case autotune 1024x1536")
+    tile = t.best_tile(1024, 1536, 8)
+    assert 1 <= tile <= len(ccl.tile_configs())
+    t2 = autotune.Autotuner(str(tmp_path / "tiles.json"))
+    assert t2.best_tile(1024, 1536, 8) == tile  # from the cache
+    imgs = [inputs.bernoulli(200 + 37 * i, 300, 0.5, seed=i, device=DEV) for i in range(6)]
+    bt = t.tune_batch(imgs, [8] * 6, key="six")
+    outs = ccl.label_batch(imgs, 8, tile=bt)
+    torch.cuda.synchronize()
+    for img, o in zip(imgs, outs):
+        assert np.array_equal(o.cpu().numpy(), _oracle(img, 8)[0])
+
+
+def test_serve_alone_equals_mix(ccl):
+    from paper_1606_05973_amd import serve
+    rng = random.Random(7)
+    pool = []
+    for i, s in enumerate(inputs.batch_specs(40, seed=11, max_side=900)):
+        pool.append((inputs.make(s, device=DEV), 8 if rng.random() < 0.5 else 4))
+    torch.cuda.synchronize()
+    srv = serve.Server(hbm_budget=256 << 20, n_streams=3, max_batch=8)
+    reqs = []
+    say("case serve 120 requests")
+    t0 = time.perf_counter()
+    for n in range(120):
+        img, conn = pool[rng.randrange(len(pool))]
+        reqs.append(srv.submit(img, conn))
+        if n % 7 == 0:
+            time.sleep(rng.random() * 0.002)
+    huge = torch.zeros((12000, 12000), dtype=torch.uint8, device=DEV)
+    rej = srv.submit(huge, 8)
+    srv.close()
+    t1 = time.perf_counter()
+    st = srv.stats(t0, t1)
+    say("serve stats", st)
+    assert rej.status == "rejected" and st["rejected"] == 1
+    assert st["completed"] == 120
+    for r in reqs:
+        assert r.status == "done"
+        alone = ccl.label(r.img, r.conn)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, r.labels), r.rid
+    for r in reqs[:10]:
+        assert np.array_equal(r.labels.cpu().numpy(), _oracle(r.img, r.conn)[0])
