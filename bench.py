@@ -58,6 +58,136 @@ def load_traffic(kernel: str, workload_key: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _median_ms(torch, fn, reps):
+    """Median over reps of fn()'s duration, HIP events on the current stream."""
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return statistics.median(ts)
+
+
+def bench_batched(torch, n, conn, reps, verify):
+    """The uneven batch: n images, one ccl_label_batch call (autotuned tile)
+    vs a loop of single ccl_label calls vs a replay of the captured graph."""
+    import tempfile
+
+    from paper_1606_05973_amd import autotune, ccl, inputs
+    dev = torch.device("cuda:0")
+    specs = inputs.batch_specs(n, seed=0)
+    imgs = [inputs.make(sp, device=dev) for sp in specs]
+    log(f"batched conn {conn}: {n} images made")
+    outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=dev) for im in imgs]
+    single = [torch.empty_like(o) for o in outs]
+    px = sum(im.numel() for im in imgs)
+    with tempfile.TemporaryDirectory() as td:
+        tile = autotune.Autotuner(os.path.join(td, "tiles.json")).tune_batch(imgs, [conn] * n)
+    log(f"batched conn {conn}: tuned tile {tile}")
+    ccl.reserve(ccl.batch_workspace_bytes([tuple(im.shape) for im in imgs], conn, tile))
+
+    def loop():
+        for im, o in zip(imgs, single):
+            ccl.label(im, conn, out=o)
+    for _ in range(2):
+        ccl.label_batch(imgs, conn, outs=outs, tile=tile)
+        loop()
+    t_batch = _median_ms(torch, lambda: ccl.label_batch(imgs, conn, outs=outs, tile=tile), reps)
+    t_loop = _median_ms(torch, loop, reps)
+    g = ccl.BatchGraph(imgs, conn, outs=outs, tile=tile)
+    g.launch()
+    t_graph = _median_ms(torch, g.launch, reps)
+    g.close()
+    torch.cuda.synchronize()
+    log(f"batched conn {conn}: timed")
+    rec = {
+        "images": n, "conn": conn, "mpx": round(px / 1e6, 2), "tile": list(ccl.tile_shape(tile, conn)),
+        "batched_gpx_per_s": round(px / (t_batch * 1e-3) / 1e9, 2),
+        "graph_gpx_per_s": round(px / (t_graph * 1e-3) / 1e9, 2),
+        "single_loop_gpx_per_s": round(px / (t_loop * 1e-3) / 1e9, 2),
+        "batched_ms": round(t_batch, 3), "graph_ms": round(t_graph, 3), "single_loop_ms": round(t_loop, 3),
+        "batched_equals_single": all(torch.equal(a, b) for a, b in zip(outs, single)),
+    }
+    if verify:
+        import numpy as np
+
+        import oracle
+        rec["bit_exact"] = all(np.array_equal(o.cpu().numpy(), oracle.cclremsp(im.cpu().numpy(), conn)[0])
+                               for im, o in zip(imgs, outs))
+    return rec
+
+
+def bench_served(torch, rates, nreq, verify):
+    """Poisson request streams through the continuous-batching server."""
+    import numpy as np
+
+    from paper_1606_05973_amd import ccl, inputs, serve
+    dev = torch.device("cuda:0")
+    _, specs = inputs.serve_specs(1, 1.0, seed=0, pool=256)
+    pool = [inputs.make(sp, device=dev) for sp in specs]
+    torch.cuda.synchronize()
+    log("served: pool made")
+    res = {"pool_images": len(pool), "requests_per_rate": nreq, "rates": {}}
+    all_ok = True
+    for rate in rates:
+        reqs, _ = inputs.serve_specs(nreq, float(rate), seed=0, pool=256)
+        kept = {}
+
+        def on_done(r):
+            if r.rid % 97 == 0:
+                kept[r.rid] = r
+            else:
+                r.labels = None
+        srv = serve.Server(hbm_budget=16 << 30, n_streams=3, max_batch=64, device=dev, on_done=on_done)
+        # warm the streams and the caching allocator outside the measurement
+        for q in reqs[:64]:
+            srv.submit(pool[q["img"]], q["conn"])
+        srv.close()
+        kept.clear()
+        srv = serve.Server(hbm_budget=16 << 30, n_streams=3, max_batch=64, device=dev, on_done=on_done)
+        t0 = time.perf_counter()
+        for q in reqs:
+            # sleep (releasing the interpreter lock to the scheduler thread)
+            # until the arrival time; requests already due go at once
+            wait = t0 + q["t"] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            srv.submit(pool[q["img"]], q["conn"])
+        srv.close()
+        t1 = max(r.t_done for r in srv.done)
+        st = srv.stats(t0, t1)
+        offered = sum(pool[q["img"]].numel() for q in reqs) / reqs[-1]["t"] / 1e9
+        ok = True
+        for rid, r in kept.items():
+            alone = ccl.label(r.img, r.conn)
+            ok &= bool(torch.equal(alone, r.labels))
+        if verify:
+            import oracle
+            for rid in sorted(kept)[:4]:
+                r = kept[rid]
+                ok &= bool(np.array_equal(r.labels.cpu().numpy(), oracle.cclremsp(r.img.cpu().numpy(), r.conn)[0]))
+        all_ok &= ok
+        log(f"served rate {rate}: {st['completed']} done, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms")
+        res["rates"][str(rate)] = {
+            "offered_gpx_per_s": round(offered, 2), "gpx_per_s": round(st["gpx_per_s"], 2),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
+            "completed": st["completed"], "batches": st["batches"],
+            "max_batches_in_flight": st["max_batches_in_flight"], "alone_equals_mix_checked": len(kept),
+        }
+        kept.clear()
+        del srv
+    res["alone_equals_mix"] = all_ok
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +204,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile configuration id (0 = default)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="images in the batched measurement (0 = skip)")
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--serve-rates", default="1000,5000,10000,20000",
+                    help="Poisson request rates (req/s) for the served measurement ('' = skip)")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="requests per rate")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a plain copy kernel "
                          "of known size, used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -196,6 +331,21 @@ def main():
             }
         if not args.no_verify:
             record["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), ref)) and int(kdev.item()) == kref
+
+    del out, img
+    torch.cuda.empty_cache()
+    ccl.release()
+    log(f"single image done: {record['value']} Gpx/s")
+    if args.batch > 0:
+        log("batched")
+        record["batched"] = [bench_batched(torch, args.batch, c, args.batch_reps, not args.no_verify)
+                             for c in (args.conn, 12 - args.conn)]
+        torch.cuda.empty_cache()
+        ccl.release()
+    rates = [int(x) for x in args.serve_rates.split(",") if x.strip()]
+    if rates and args.serve_requests > 0:
+        log("served")
+        record["served"] = bench_served(torch, rates, args.serve_requests, not args.no_verify)
 
     print(json.dumps(record), flush=True)
 

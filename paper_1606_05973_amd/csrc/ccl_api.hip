@@ -215,9 +215,9 @@ struct PhaseMarks {
 };
 
 // Workgroups of a persistent launch of `kernel`: as many as can be resident
-// at once (occupancy x CUs), computed once per kernel.
-template <class K>
-int persistent_groups(K kernel, int threads) {
+// at once (occupancy x CUs), computed once per kernel instantiation.
+template <auto kernel>
+int persistent_groups(int threads) {
     static int n = 0;
     if (n == 0) {
         int dev = 0, cus = 0, per_cu = 0;
@@ -252,7 +252,7 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
     pm.mark();
     hipLaunchKernelGGL((k_relabel<NSR, TW, BH>),
-                       dim3((uint32_t)std::min<int64_t>(tiles, persistent_groups(k_relabel<NSR, TW, BH>, kTileThreads))),
+                       dim3((uint32_t)std::min<int64_t>(tiles, persistent_groups<k_relabel<NSR, TW, BH>>(kTileThreads))),
                        dim3(kTileThreads), 0, s, b, (int32_t)tiles);
     pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;

@@ -384,16 +384,26 @@ __device__ int32_t number_runs(RunLds<NSR, TW, BH> &t) {
 // K1: tile scan.
 // ------------------------------------------------------------------------
 template <int NSR, int TW, int BH>
-struct ScanLds : RunLds<NSR, TW, BH> {
+struct ScanLate {
     using G = Geo<NSR, TW, BH>;
-    int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
     uint16_t RT[G::RCAP];   // component ordinal of each node
-    uint16_t SP[G::RCAP];   // start of each node: block row * TW + column
     uint32_t RRB[G::RW];    // node lies in the block row of its root (bit per node)
     uint32_t RFB[G::RW];    // root nodes (bit per node); later boundary components (bit per component)
     int32_t RFP[G::RW];
     uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
     int32_t rowcnt[G::TH];
+};
+
+template <int NSR, int TW, int BH>
+struct ScanLds : RunLds<NSR, TW, BH> {
+    using G = Geo<NSR, TW, BH>;
+    static constexpr int PRCAP = (int)(sizeof(ScanLate<NSR, TW, BH>) / 4);
+    int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
+    uint16_t SP[G::RCAP];   // start of each node: block row * TW + column
+    union {
+        uint32_t PR[PRCAP];  // during the union step: touching node pairs (x | y << 16)
+        ScanLate<NSR, TW, BH> late;
+    };
 };
 
 template <int NSR, int TW, int BH>
@@ -416,23 +426,18 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     const int tid = threadIdx.x;
     const bool conn8 = BH == 2;
 
-    // 1. foreground masks (kept in LDS and stored for the labeling pass)
-    uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+    // 1. foreground masks (kept in LDS; stored for the labeling pass at the
+    // end, so that no barrier waits on those stores)
+    uint32_t mreg[MPT];
 #pragma unroll
     for (int k = 0; k < MPT; k++) {
         const int i = tid + k * NT;
         if (i < G::NM) {
             const int r = i / NW, w = i % NW;
-            uint32_t m = load_word(im, y0 + r, x0 + (w << 5));
-            t.M[i] = m;
-            gmask[i] = m;
-            t.RK[i] = 0u;
+            mreg[k] = load_word(im, y0 + r, x0 + (w << 5));
+            t.M[i] = mreg[k];
         }
     }
-    for (int r = tid; r < TH; r += NT)
-        t.rowcnt[r] = 0;
-    for (int i = tid; i < G::RW; i += NT)
-        t.RFB[i] = 0u;
     __syncthreads();
 
     // 2. block runs, their ordinals and start positions
@@ -460,97 +465,136 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     // of row runs is met exactly once: U1 at the first column of their
     // overlap, U2 (8-conn) where the upper run starts just right of the
     // lower one's end, U3 (8-conn) where the lower run starts just right of
-    // the upper one's end.
+    // the upper one's end.  The contacts are first listed as node pairs
+    // (compacted by a block scan), then the pairs are dealt out evenly to
+    // the threads, which apply Rem's union with splicing to them.  A tile
+    // with more contacts than the list holds is done in several rounds.
+    uint64_t cm1[UPT2];  // U1 positions (low half; partner at c) and U3 (high half; partner at c-1)
+    uint32_t cm2[UPT2];  // U2 positions (partner at c+1)
+    int32_t coff[UPT2];
+    int32_t n_pairs = 0;
 #pragma unroll
     for (int k = 0; k < UPT2; k++) {
         const int v = tid + k * NT;
         const int u = v % G::NU, h = v / G::NU;
-        if (h >= LPU)
-            continue;
         const int R = u / NW, w = u % NW;
-        if (R == 0)
-            continue;
-        const int rm = R * BH, ru = R * BH - 1;
-        const uint32_t m = t.M[rm * NW + w];
-        const uint32_t mL = w ? t.M[rm * NW + w - 1] : 0u;
-        const uint32_t mR = (w < NW - 1) ? t.M[rm * NW + w + 1] : 0u;
-        const uint32_t up = t.M[ru * NW + w];
-        const uint32_t uL = w ? t.M[ru * NW + w - 1] : 0u;
-        const uint32_t uR = (w < NW - 1) ? t.M[ru * NW + w + 1] : 0u;
-        const uint32_t o = m & up;
-        const uint32_t u1 = o & ~((o << 1) | ((mL & uL) >> 31));
-        uint32_t u2 = 0u, u3 = 0u;
-        if (conn8) {
-            const uint32_t mn = (m >> 1) | (mR << 31);
-            const uint32_t un = (up >> 1) | (uR << 31);
-            const uint32_t mp = (m << 1) | (mL >> 31);
-            const uint32_t upp = (up << 1) | (uL >> 31);
-            u2 = m & ~mn & ~up & un;
-            u3 = m & ~mp & ~up & upp;
+        cm1[k] = 0;
+        cm2[k] = 0u;
+        if (h < LPU && R > 0) {
+            const int rm = R * BH, ru = R * BH - 1;
+            const uint32_t m = t.M[rm * NW + w];
+            const uint32_t mL = w ? t.M[rm * NW + w - 1] : 0u;
+            const uint32_t up = t.M[ru * NW + w];
+            const uint32_t uL = w ? t.M[ru * NW + w - 1] : 0u;
+            const uint32_t o = m & up;
+            const uint32_t u1 = o & ~((o << 1) | ((mL & uL) >> 31));
+            uint32_t u2 = 0u, u3 = 0u;
+            if (conn8) {
+                const uint32_t mR = (w < NW - 1) ? t.M[rm * NW + w + 1] : 0u;
+                const uint32_t uR = (w < NW - 1) ? t.M[ru * NW + w + 1] : 0u;
+                const uint32_t mn = (m >> 1) | (mR << 31);
+                const uint32_t un = (up >> 1) | (uR << 31);
+                const uint32_t mp = (m << 1) | (mL >> 31);
+                const uint32_t upp = (up << 1) | (uL >> 31);
+                u2 = m & ~mn & ~up & un;
+                u3 = m & ~mp & ~up & upp;
+            }
+            // this thread's share of the word's contact positions
+            constexpr int PART = 32 / LPU;
+            const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
+            cm1[k] = (uint64_t)(u1 & mine) | ((uint64_t)(u3 & mine) << 32);
+            cm2[k] = u2 & mine;
         }
-        // this thread's share of the word's contact positions
-        constexpr int PART = 32 / LPU;
-        const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
-        uint64_t cm1 = (uint64_t)(u1 & mine) | ((uint64_t)(u3 & mine) << 32);  // partner at c (U1) or c-1 (U3)
-        uint32_t cm2 = u2 & mine;                                              // partner at c+1 (U2)
-        if (!cm1 && !cm2)
-            continue;
-        const uint32_t sR = t.S[u];
-        const int32_t bR = t.base[u] - 1;
-        const int uu = u - NW;
-        const uint32_t sU = t.S[uu];
-        const int32_t bU = t.base[uu] - 1;
-        const uint32_t sUL = w ? t.S[uu - 1] : 0u;
-        const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
-        const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
-        const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
-        // One flat loop: each lane steps its own union (one load pair and one
-        // CAS per step) and takes its next contact as soon as the current
-        // union ends, so lanes never wait for each other's unions.
-        bool busy = false;
-        int32_t rx = 0, ry = 0;
-        for (;;) {
-            if (!busy) {
-                if (!cm1 && !cm2)
-                    break;
+        int32_t tot;
+        coff[k] = n_pairs + block_exclusive_scan<NT>(__popcll(cm1[k]) + __popc(cm2[k]), &tot);
+        n_pairs += tot;
+    }
+    for (int r0 = 0; r0 < n_pairs; r0 += ScanLds<NSR, TW, BH>::PRCAP) {
+        const int r1 = r0 + ScanLds<NSR, TW, BH>::PRCAP;
+#pragma unroll
+        for (int k = 0; k < UPT2; k++) {
+            int32_t idx = coff[k];
+            uint64_t a = cm1[k];
+            uint32_t c2 = cm2[k];
+            if ((!a && !c2) || idx >= r1)
+                continue;
+            const int u = (tid + k * NT) % G::NU;
+            const int w = u % NW;
+            const uint32_t sR = t.S[u];
+            const int32_t bR = t.base[u] - 1;
+            const int uu = u - NW;
+            const uint32_t sU = t.S[uu];
+            const int32_t bU = t.base[uu] - 1;
+            const uint32_t sUL = w ? t.S[uu - 1] : 0u;
+            const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
+            const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
+            const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
+            while ((a || c2) && idx < r1) {
                 int c, d;
-                if (cm1) {
-                    const int bit = __ffsll((unsigned long long)cm1) - 1;
-                    cm1 &= cm1 - 1;
+                if (a) {
+                    const int bit = __ffsll((unsigned long long)a) - 1;
+                    a &= a - 1;
                     c = bit & 31;
                     d = (bit >> 5) ? -1 : 0;
                 } else {
-                    c = __ffs(cm2) - 1;
-                    cm2 &= cm2 - 1u;
+                    c = __ffs(c2) - 1;
+                    c2 &= c2 - 1u;
                     d = 1;
                 }
-                rx = bR + __popc(sR & mask_le(c));
-                const int p = c + d;
-                const uint32_t sp = p < 0 ? sUL : (p > 31 ? sUR : sU);
-                const int32_t bp = p < 0 ? bUL : (p > 31 ? bUR : bU);
-                ry = bp + __popc(sp & mask_le(p & 31));
-                busy = true;
-            }
-            const int32_t px = aload<WG>(t.P + rx);
-            const int32_t py = aload<WG>(t.P + ry);
-            if (px == py) {
-                busy = false;
-                continue;
-            }
-            const bool xs = px > py;
-            const int32_t n = xs ? rx : ry;
-            const int32_t pn = xs ? px : py;
-            const int32_t seen = acas<WG>(t.P + n, pn, xs ? py : px);
-            if (seen == pn) {
-                if (pn == n) {
-                    busy = false;
-                    continue;
+                if (idx >= r0) {
+                    const int32_t x = bR + __popc(sR & mask_le(c));
+                    const int pc = c + d;
+                    const uint32_t sp = pc < 0 ? sUL : (pc > 31 ? sUR : sU);
+                    const int32_t bp = pc < 0 ? bUL : (pc > 31 ? bUR : bU);
+                    const int32_t y = bp + __popc(sp & mask_le(pc & 31));
+                    t.PR[idx - r0] = (uint32_t)x | ((uint32_t)y << 16);
                 }
-                rx = xs ? pn : rx;
-                ry = xs ? ry : pn;
+                idx++;
             }
         }
+        __syncthreads();
+        // Each lane steps its own union (one load pair and one CAS per step)
+        // and takes its next pair as soon as the current union ends.
+        const int np = min(n_pairs - r0, ScanLds<NSR, TW, BH>::PRCAP);
+        int q = tid;
+        int32_t rx = 0, ry = 0;
+        if (q < np) {
+            const uint32_t pr = t.PR[q];
+            rx = (int32_t)(pr & 0xFFFFu);
+            ry = (int32_t)(pr >> 16);
+        }
+        while (q < np) {
+            const int32_t px = aload<WG>(t.P + rx);
+            const int32_t py = aload<WG>(t.P + ry);
+            bool next = px == py;
+            if (!next) {
+                const bool xs = px > py;
+                const int32_t n = xs ? rx : ry;
+                const int32_t pn = xs ? px : py;
+                const int32_t seen = acas<WG>(t.P + n, pn, xs ? py : px);
+                if (seen == pn) {
+                    next = pn == n;
+                    rx = xs ? pn : rx;
+                    ry = xs ? ry : pn;
+                }
+            }
+            if (next) {
+                q += NT;
+                if (q < np) {
+                    const uint32_t pr = t.PR[q];
+                    rx = (int32_t)(pr & 0xFFFFu);
+                    ry = (int32_t)(pr >> 16);
+                }
+            }
+        }
+        __syncthreads();
     }
+    for (int i = tid; i < G::NM; i += NT)
+        t.late.RK[i] = 0u;
+    for (int r = tid; r < TH; r += NT)
+        t.late.rowcnt[r] = 0;
+    for (int i = tid; i < G::RW; i += NT)
+        t.late.RFB[i] = 0u;
     __syncthreads();
 
     // 4. flatten; roots are numbered in node order (local components).  A
@@ -565,27 +609,27 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
         const uint64_t bal = __ballot(root);
         const int wd = (k0 + wave * 64) >> 5;
         if (lane == 0 && wd < G::RW)
-            t.RFB[wd] = (uint32_t)bal;
+            t.late.RFB[wd] = (uint32_t)bal;
         if (lane == 32 && wd + 1 < G::RW)
-            t.RFB[wd + 1] = (uint32_t)(bal >> 32);
+            t.late.RFB[wd + 1] = (uint32_t)(bal >> 32);
     }
     __syncthreads();
-    const int32_t n_comp = popcount_prefix<NT>(t.RFB, t.RFP, (n_runs + 31) >> 5);
+    const int32_t n_comp = popcount_prefix<NT>(t.late.RFB, t.late.RFP, (n_runs + 31) >> 5);
     __syncthreads();
     for (int k0 = 0; k0 < n_runs; k0 += NT) {
         const int k = k0 + tid;
         bool same_row = false;
         if (k < n_runs) {
             const int32_t root = t.P[k];
-            t.RT[k] = (uint16_t)rank_of(t.RFB, t.RFP, root);
+            t.late.RT[k] = (uint16_t)rank_of(t.late.RFB, t.late.RFP, root);
             same_row = (t.SP[k] / TW) == (t.SP[root] / TW);
         }
         const uint64_t bal = __ballot(same_row);
         const int wd = (k0 + wave * 64) >> 5;
         if (lane == 0 && wd < G::RW)
-            t.RRB[wd] = (uint32_t)bal;
+            t.late.RRB[wd] = (uint32_t)bal;
         if (lane == 32 && wd + 1 < G::RW)
-            t.RRB[wd + 1] = (uint32_t)(bal >> 32);
+            t.late.RRB[wd + 1] = (uint32_t)(bal >> 32);
     }
     __syncthreads();
 
@@ -594,14 +638,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     for (int c = tid; c < n_comp; c += NT)
         t.P[c] = 0x7FFFFFFF;
     for (int i = tid; i < G::RW; i += NT)
-        t.RFB[i] = 0u;  // from here on: boundary components
+        t.late.RFB[i] = 0u;  // from here on: boundary components
     __syncthreads();
     for (int k = tid; k < n_runs; k += NT) {
         const int sp = t.SP[k];
         const int R = sp / TW, col = sp % TW;
         // the first pixel of a component lies in the block row of its root
         // (the root is its first node in block-row order)
-        if (!((t.RRB[k >> 5] >> (k & 31)) & 1u))
+        if (!((t.late.RRB[k >> 5] >> (k & 31)) & 1u))
             continue;
         int32_t key;
         if (BH == 1) {
@@ -623,7 +667,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
                 from = 0;
             }
         }
-        atomicMin(&t.P[t.RT[k]], key);
+        atomicMin(&t.P[t.late.RT[k]], key);
     }
     __syncthreads();
 
@@ -641,8 +685,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             while (starts) {
                 const int bb = __ffs(starts) - 1;
                 starts &= starts - 1u;
-                const int32_t comp = t.RT[node_at(t, R, (w << 5) + bb)];
-                atomicOr(&t.RFB[comp >> 5], 1u << (comp & 31));
+                const int32_t comp = t.late.RT[node_at(t, R, (w << 5) + bb)];
+                atomicOr(&t.late.RFB[comp >> 5], 1u << (comp & 31));
             }
         } else {
             const int q = i - 2 * NW, side = q / TH, r = q % TH;
@@ -651,17 +695,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             const int c = side ? TW - 1 : 0;
             if (!((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u))
                 continue;
-            const int32_t comp = t.RT[node_at(t, r / BH, c)];
-            atomicOr(&t.RFB[comp >> 5], 1u << (comp & 31));
+            const int32_t comp = t.late.RT[node_at(t, r / BH, c)];
+            atomicOr(&t.late.RFB[comp >> 5], 1u << (comp & 31));
         }
     }
     __syncthreads();
-    const int32_t n_bound = popcount_prefix<NT>(t.RFB, t.RFP, (n_comp + 31) >> 5);
+    const int32_t n_bound = popcount_prefix<NT>(t.late.RFB, t.late.RFP, (n_comp + 31) >> 5);
     for (int c = tid; c < n_comp; c += NT) {
-        if (!((t.RFB[c >> 5] >> (c & 31)) & 1u)) {
+        if (!((t.late.RFB[c >> 5] >> (c & 31)) & 1u)) {
             const int32_t key = t.P[c];
-            atomicOr(&t.RK[key >> 5], 1u << (key & 31));
-            atomicAdd(&t.rowcnt[key / TW], 1);
+            atomicOr(&t.late.RK[key >> 5], 1u << (key & 31));
+            atomicAdd(&t.late.rowcnt[key / TW], 1);
         }
     }
     __syncthreads();
@@ -669,14 +713,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     // 7. exports
     const int64_t cbase = (int64_t)ti * G::CAP;
     for (int c = tid; c < n_comp; c += NT) {
-        if ((t.RFB[c >> 5] >> (c & 31)) & 1u) {
-            const int32_t j = rank_of(t.RFB, t.RFP, c);
+        if ((t.late.RFB[c >> 5] >> (c & 31)) & 1u) {
+            const int32_t j = rank_of(t.late.RFB, t.late.RFP, c);
             const int32_t key = t.P[c];
             const int kr = key / TW, kc = key % TW;
             const uint32_t id = (uint32_t)(cbase + j);
             const uint32_t gkey = (uint32_t)((y0 + kr) * im.W + x0 + kc);
             im.bkey[id] = (uint16_t)key;
-            im.bval[id] = popc_before(&t.RK[kr * NW], kc);
+            im.bval[id] = popc_before(&t.late.RK[kr * NW], kc);
             im.uf[id] = ((uint64_t)gkey << 32) | id;
         }
     }
@@ -702,25 +746,32 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             continue;
         uint16_t v = kNone;
         if ((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u)
-            v = (uint16_t)rank_of(t.RFB, t.RFP, t.RT[node_at(t, r / BH, c)]);
+            v = (uint16_t)rank_of(t.late.RFB, t.late.RFP, t.late.RT[node_at(t, r / BH, c)]);
         *dst = v;
     }
     for (int r = tid; r < TH; r += NT)
         if (y0 + r < im.H)
-            im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.rowcnt[r];
+            im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.late.rowcnt[r];
     uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
     for (int k = tid; k < n_runs; k += NT)
-        grt[k] = t.RT[k];
+        grt[k] = t.late.RT[k];
     int32_t *gck = im.cf + (int64_t)ti * G::RCAP;
     for (int c = tid; c < n_comp; c += NT)
         gck[c] = t.P[c];
     uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
     for (int i = tid; i < ((n_comp + 31) >> 5); i += NT)
-        gcb[i] = t.RFB[i];
+        gcb[i] = t.late.RFB[i];
     if (tid == 0) {
         im.tcnt[ti * 4 + 0] = n_runs;
         im.tcnt[ti * 4 + 1] = n_comp;
         im.tcnt[ti * 4 + 2] = n_bound;
+    }
+    uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+#pragma unroll
+    for (int k = 0; k < MPT; k++) {
+        const int i = tid + k * NT;
+        if (i < G::NM)
+            gmask[i] = mreg[k];
     }
 }
 
@@ -1060,16 +1111,27 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     const int wave = tid >> 6, lane = tid & 63;
     // Persistent: each workgroup walks tiles blockIdx.x, +gridDim.x, ...
     // While a tile's stores drain, the next tile's mask and tables are
-    // already in flight into registers.
+    // already in flight into registers, and the node and component counts
+    // of the tile after it (which size those table loads) too, so no load
+    // waits on another.
     uint32_t pm[MPT];
     uint32_t prt[TPT];
     int32_t pcf[TPT];
-    int pn_runs = 0, pn_comp = 0;
+    int pn_runs = 0, pn_comp = 0;   // counts of the tile whose tables are in registers
+    int qn_runs = 0, qn_comp = 0;   // counts of the tile after it
+    auto counts = [&](int tile) {
+        if (tile < ntiles) {
+            const Img &im = find_img(b, tile, kTile);
+            const int ti = tile - im.tile0;
+            qn_runs = im.tcnt[ti * 4 + 0];
+            qn_comp = im.tcnt[ti * 4 + 1];
+        }
+    };
     auto fetch = [&](int tile) {
         const Img &im = find_img(b, tile, kTile);
         const int ti = tile - im.tile0;
-        pn_runs = im.tcnt[ti * 4 + 0];
-        pn_comp = im.tcnt[ti * 4 + 1];
+        pn_runs = qn_runs;
+        pn_comp = qn_comp;
         const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
 #pragma unroll
         for (int k = 0; k < MPT; k++) {
@@ -1086,8 +1148,11 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         }
     };
     int tile = blockIdx.x;
-    if (tile < ntiles)
+    if (tile < ntiles) {
+        counts(tile);
         fetch(tile);
+        counts(tile + gridDim.x);
+    }
     for (; tile < ntiles; tile += gridDim.x) {
         const Img &im = find_img(b, tile, kTile);
         const int ti = tile - im.tile0;
@@ -1112,8 +1177,10 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         for (int k = tid; k < pn_runs; k += NT)
             t.RF[k] = t.CF[t.RT[k]];
         __syncthreads();
-        if (tile + (int)gridDim.x < ntiles)
+        if (tile + (int)gridDim.x < ntiles) {
             fetch(tile + gridDim.x);
+            counts(tile + 2 * (int)gridDim.x);
+        }
 
         // write: one tile row segment of 256 pixels per wave instruction
         const bool vec_ok = ((im.W & 3) == 0) && ((reinterpret_cast<uintptr_t>(im.labels) & 15u) == 0);

@@ -24,6 +24,9 @@ largest is 465.20 MB, Table III).  Those images are not available here:
 * ``batch_specs`` -- the uneven batch mix: side H log-uniform in [64, 4096],
   aspect log-uniform in [0.25, 4], W = clamp(round(H*aspect), 64, 4096);
   content Bernoulli p ~ U[0.2, 0.8] or GRF sigma ~ U[1, 16] at q = 0.5.
+* ``serve_specs`` -- a request stream for the server: Poisson arrival times
+  at a given rate, 95% of sizes as in ``batch_specs`` and 5% with sides
+  log-uniform up to 8192, connectivity 4 or 8 with equal probability.
 """
 from __future__ import annotations
 
@@ -104,11 +107,21 @@ def _uniform01(H: int, W: int, seed: int, device) -> torch.Tensor:
 
 def grf(H: int, W: int, sigma: float, q: float = 0.5, seed: int = 0, device="cpu",
         stride: int | None = None) -> torch.Tensor:
-    """Thresholded periodic Gaussian random field (foreground fraction ~ 1-q)."""
+    """Thresholded periodic Gaussian random field (foreground fraction ~ 1-q).
+
+    The smoothing of fields up to 2**24 pixels runs on the CPU: a GPU FFT
+    compiles kernels for every new size, which would dominate the cost of
+    building an uneven batch.  Larger fields are smoothed on `device`.
+    (Float rounding may differ between the two, so the bytes of one spec can
+    differ by device; consumers label the same bytes on both sides.)"""
+    dst = device
     u1 = _uniform01(H, W, seed, device)
     u2 = _uniform01(H, W, seed ^ 0x5DEECE66D, device)
     noise = (torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)).to(torch.float32)
     del u1, u2
+    if H * W <= (1 << 24):
+        device = "cpu"
+        noise = noise.to(device)
     fy = torch.fft.fftfreq(H, device=device, dtype=torch.float32)
     fx = torch.fft.rfftfreq(W, device=device, dtype=torch.float32)
     s2 = 2.0 * (math.pi * sigma) ** 2
@@ -118,7 +131,7 @@ def grf(H: int, W: int, sigma: float, q: float = 0.5, seed: int = 0, device="cpu
     flat = field.reshape(-1)
     step = max(1, flat.numel() // (1 << 22))
     thr = torch.quantile(flat[::step].to(torch.float64), q).to(torch.float32)
-    out = _alloc(H, W, stride, device)
+    out = _alloc(H, W, stride, dst)
     out.copy_((field > thr).to(torch.uint8))
     return out
 
@@ -189,6 +202,30 @@ def batch_specs(n: int, seed: int = 0, min_side: int = 64, max_side: int = 4096)
             specs.append(dict(H=H, W=W, kind="grf", param=float(rng.uniform(1.0, 16.0)),
                               seed=seed * 100003 + i))
     return specs
+
+
+def serve_specs(n: int, rate: float, seed: int = 0, pool: int = 0, large_frac: float = 0.05,
+                large_max: int = 8192):
+    """A seeded request stream: list of dicts (t, img index or spec, conn).
+
+    Arrival times t (seconds from 0) are a Poisson process of intensity
+    ``rate``.  With ``pool`` > 0 the requests pick images from a pool of
+    that many specs (returned separately) instead of carrying one each, so a
+    long stream needs only a bounded set of device images.  Returns
+    (requests, specs)."""
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0x5EED))
+    m = pool if pool > 0 else n
+    specs = batch_specs(m, seed=seed)
+    for i in range(m):
+        if rng.uniform() < large_frac:
+            H = int(round(math.exp(rng.uniform(math.log(64), math.log(large_max)))))
+            a = math.exp(rng.uniform(math.log(0.25), math.log(4.0)))
+            specs[i] = dict(specs[i], H=H, W=int(min(max(round(H * a), 64), large_max)))
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    which = rng.integers(0, m, size=n) if pool > 0 else np.arange(n)
+    conns = np.where(rng.uniform(size=n) < 0.5, 4, 8)
+    reqs = [dict(t=float(t[i]), img=int(which[i]), conn=int(conns[i])) for i in range(n)]
+    return reqs, specs
 
 
 def make(spec: dict, device="cpu", stride: int | None = None) -> torch.Tensor:

@@ -54,13 +54,21 @@ class Request:
 
 class Server:
     def __init__(self, hbm_budget: int = 8 << 30, n_streams: int = 3, max_batch: int = 64,
-                 max_batch_pixels: int = 96 << 20, tile: int = 0, device="cuda:0"):
+                 max_batch_pixels: int = 96 << 20, tile: int = 0, device="cuda:0", on_done=None):
         self.budget = int(hbm_budget)
+        self.on_done = on_done      # called with each finished Request, on the scheduler thread
         self.max_batch = max_batch
         self.max_batch_pixels = max_batch_pixels
         self.tile = tile
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        # Grow each stream's library workspace once, up front, to what a full
+        # batch needs, so that serving never waits on a reallocation.
+        side = int(max_batch_pixels ** 0.5) + 1
+        ws = ccl.batch_workspace_bytes([(side, side)] * 2, 4, tile) + max_batch * (1 << 20)
+        with torch.cuda.device(self.device):
+            for st in self.streams:
+                ccl.reserve(ws, st)
         self.free_streams = list(range(n_streams))
         self.pending = collections.deque()
         self.inflight = []          # (stream index, event, [requests], footprint)
@@ -132,6 +140,8 @@ class Server:
                     r.t_done = now
                     r.status = "done"
                     r._done.set()
+                    if self.on_done is not None:
+                        self.on_done(r)
                 self.done.extend(reqs)
                 self.used -= fp
                 self.free_streams.append(si)
