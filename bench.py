@@ -195,7 +195,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=21568, help="image side (square)")
     ap.add_argument("--p", type=float, default=0.5, help="Bernoulli foreground probability")
-    ap.add_argument("--content", choices=["bernoulli", "grf"], default="bernoulli")
+    ap.add_argument("--content", choices=["bernoulli", "grf", "gray"], default="bernoulli",
+                    help="gray: grayscale bytes binarized inside the labeling at --level")
+    ap.add_argument("--level", type=int, default=None,
+                    help="foreground iff byte > level (default 0 = nonzero; 127 for --content gray)")
     ap.add_argument("--sigma", type=float, default=8.0, help="GRF smoothing (px) when --content grf")
     ap.add_argument("--q", type=float, default=0.5, help="GRF threshold quantile when --content grf")
     ap.add_argument("--pitch", type=int, default=0,
@@ -226,9 +229,13 @@ def main():
     dev = torch.device("cuda:0")
     S = args.size
     stride = S if args.pitch <= 0 else (S + args.pitch - 1) // args.pitch * args.pitch
+    level = args.level if args.level is not None else (127 if args.content == "gray" else 0)
     if args.content == "grf":
         img = inputs.grf(S, S, args.sigma, args.q, seed=0, device=dev, stride=stride)
         content = f"thresholded Gaussian random field sigma={args.sigma} q={args.q} seed 0"
+    elif args.content == "gray":
+        img = inputs.gray(S, S, args.sigma, seed=0, device=dev, stride=stride)
+        content = f"grayscale Gaussian field sigma={args.sigma} seed 0"
     else:
         img = inputs.bernoulli(S, S, args.p, seed=0, device=dev, stride=stride)
         content = f"Bernoulli p={args.p} seed 0"
@@ -238,7 +245,7 @@ def main():
     th, tw = ccl.tile_shape(args.tile, args.conn)
 
     for _ in range(args.warmup):
-        ccl.label(img, args.conn, out=out, tile=args.tile)
+        ccl.label(img, args.conn, out=out, tile=args.tile, level=level)
     torch.cuda.synchronize()
 
     ccl.profile(True)
@@ -249,7 +256,7 @@ def main():
     t0 = time.perf_counter()
     start.record()
     for _ in range(args.steps):
-        ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kdev)
+        ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kdev, level=level)
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -271,7 +278,8 @@ def main():
     dom_ms = phase_ms[dom]
     alg_bytes = PHASE_BYTES_PER_PX[dom] * px
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
-    workload_key = (f"bernoulli{args.p}" if args.content == "bernoulli" else f"grf{args.sigma}_{args.q}") + \
+    workload_key = {"bernoulli": f"bernoulli{args.p}", "grf": f"grf{args.sigma}_{args.q}",
+                    "gray": f"gray{args.sigma}_level{level}"}[args.content] + \
         f"_{S}x{S}_conn{args.conn}_tile{th}x{tw}" + (f"_pitch{stride}" if stride != S else "")
     traffic = load_traffic(dom, workload_key)
 
@@ -289,8 +297,10 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": f"{S}x{S} uint8 {content}, {args.conn}-connectivity, canonical int32 labels",
+            "workload": f"{S}x{S} uint8 {content}, {args.conn}-connectivity, canonical int32 labels"
+                        + (f", foreground iff byte > {level}" if level else ""),
             "H": S, "W": S, "stride": stride, "conn": args.conn, "tile": [th, tw], "parallelism": "single GPU",
+            "level": level,
         },
         "roofline": {
             "bound": "hbm",
@@ -314,6 +324,8 @@ def main():
 
         import oracle
         host = img.cpu().numpy()  # H x W view (row pitch dropped on copy)
+        if level:
+            host = oracle.binarize(host, level)
         times, ref = [], None
         for _ in range(max(args.cpu_runs, 1)):
             t = time.perf_counter()

@@ -46,7 +46,8 @@ typedef enum {
     CCL_ERR_HIP = -7,       /* a HIP runtime call or kernel launch failed       */
     CCL_ERR_TILE = -8,      /* unknown tile configuration id                    */
     CCL_ERR_CAPTURE = -9,   /* workspace must grow while the stream is captured */
-    CCL_ERR_BATCH = -10     /* n < 0, or descs NULL with n > 0                  */
+    CCL_ERR_BATCH = -10,    /* n < 0, or descs NULL with n > 0                  */
+    CCL_ERR_LEVEL = -11     /* threshold level outside 0..255                   */
 } ccl_status;
 
 /*
@@ -82,13 +83,28 @@ int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn
 int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
                  int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
 
-/* One image of a batch; fields as in ccl_label_ex. */
+/*
+ * ccl_label_level -- as ccl_label_ex, on a grayscale image binarized inside
+ * the labeling: a pixel is foreground iff its byte is greater than `level`
+ * (0..255).  This is the binarization step that precedes labeling in the
+ * paper's experiments (Section V: each image is converted to binary with a
+ * luminance threshold of 0.5); fused into the image read, it costs no extra
+ * memory traffic.  A fractional threshold f of the full range (a pixel v is
+ * foreground iff v > f * 255) is level = floor(f * 255), so f = 0.5 is
+ * level 127.  level 0 is the nonzero test of ccl_label; level 255 makes
+ * every pixel background.  Returns CCL_ERR_LEVEL for a level outside 0..255.
+ */
+int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
+                    int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
+
+/* One image of a batch; fields as in ccl_label_level. */
 typedef struct {
     const uint8_t *img;      /* device */
     int64_t H, W, stride;
     int conn;                /* 4 or 8, may differ between images */
     int32_t *labels;         /* device, dense H x W */
     int32_t *num_components; /* device or NULL */
+    int level;               /* foreground iff byte > level; 0 = nonzero */
 } ccl_image_desc;
 
 /*

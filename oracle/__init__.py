@@ -18,7 +18,8 @@ canonical(labels)            -> (labels, K)             rank by first raster ind
 merge_pairs(p, pairs)        -> p                       Algorithm 2 on a parent array
 merger_pairs(p, pairs)       -> p                       Algorithm 8 (sequential schedule)
 flatten(p, count)            -> (p, K)                  Algorithm 3
-label(img, conn)             -> labels                  the reference labeling (CCLRemSP)
+label(img, conn, level)      -> labels                  the reference labeling (CCLRemSP)
+binarize(img, level)         -> uint8 0/1               Section V thresholding
 
 All labelings returned by ``cclremsp``, ``aremsp`` and ``paremsp`` use the
 canonical numbering: 0 is background and component k (1-based) is the k-th
@@ -163,6 +164,16 @@ def flatten(p, count: int):
     return p, int(k)
 
 
-def label(img, conn: int = 8):
-    """The reference labeling used for parity: CCLRemSP output."""
+def binarize(img, level: int):
+    """Section V: every test image is turned into a binary image by a
+    luminance threshold before labeling.  On bytes: foreground (1) iff the
+    byte is greater than ``level``."""
+    return (np.asarray(img).astype(np.int32) > int(level)).astype(np.uint8)
+
+
+def label(img, conn: int = 8, level: int | None = None):
+    """The reference labeling used for parity: CCLRemSP output (of the
+    binarized image when ``level`` is given)."""
+    if level is not None:
+        img = binarize(img, level)
     return cclremsp(img, conn)[0]

@@ -28,13 +28,17 @@ _stream = ctypes.c_void_p
 class ImageDesc(ctypes.Structure):
     """ccl_image_desc of include/ccl.h."""
     _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
-                ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p)]
+                ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p),
+                ("level", ctypes.c_int)]
 
 
 _lib.ccl_label.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _stream]
 _lib.ccl_label.restype = ctypes.c_int
 _lib.ccl_label_ex.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _i32p, ctypes.c_int, _stream]
 _lib.ccl_label_ex.restype = ctypes.c_int
+_lib.ccl_label_level.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                 _stream]
+_lib.ccl_label_level.restype = ctypes.c_int
 _lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int, _stream]
 _lib.ccl_label_batch.restype = ctypes.c_int
 _lib.ccl_workspace_bytes.argtypes = [_i64, _i64, ctypes.c_int, ctypes.c_int]
@@ -67,7 +71,7 @@ CCL_OK = 0
 STATUS = {
     "CCL_ERR_NULL": -1, "CCL_ERR_SHAPE": -2, "CCL_ERR_STRIDE": -3, "CCL_ERR_CONN": -4,
     "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
-    "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10,
+    "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11,
 }
 
 
@@ -119,9 +123,17 @@ def tile_configs():
     return out
 
 
+def level_of(fraction: float) -> int:
+    """Byte level of a fractional threshold of the full range: v > fraction*255
+    iff v > level_of(fraction) for every byte v (0.5 -> 127)."""
+    import math
+    return min(255, max(0, int(math.floor(fraction * 255))))
+
+
 def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
-          num_components: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Canonical int32 labels of a 2-D uint8 device image (nonzero = foreground)."""
+          num_components: torch.Tensor | None = None, stream=None, level: int = 0) -> torch.Tensor:
+    """Canonical int32 labels of a 2-D uint8 device image; foreground iff the
+    byte exceeds `level` (0 = nonzero)."""
     H, W, stride = _img_geometry(img)
     if out is None:
         out = torch.empty((H, W), dtype=torch.int32, device=img.device)
@@ -132,8 +144,8 @@ def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, til
         if num_components.dtype != torch.int32 or num_components.numel() < 1 or not num_components.is_cuda:
             raise ValueError("num_components must be a device int32 tensor")
         nc = num_components.data_ptr()
-    st = _lib.ccl_label_ex(img.data_ptr(), H, W, stride, int(conn), out.data_ptr(), nc or None,
-                           int(tile), _stream_handle(stream))
+    st = _lib.ccl_label_level(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc or None,
+                              int(tile), _stream_handle(stream))
     _check(st)
     return out
 
@@ -143,7 +155,7 @@ def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: 
     return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
 
 
-def _descs(imgs, conns, outs, counts):
+def _descs(imgs, conns, outs, counts, levels=None):
     n = len(imgs)
     arr = (ImageDesc * max(n, 1))()
     for i, img in enumerate(imgs):
@@ -153,23 +165,25 @@ def _descs(imgs, conns, outs, counts):
         arr[i].conn = int(conns[i])
         arr[i].labels = outs[i].data_ptr()
         arr[i].num_components = counts[i].data_ptr() if counts is not None else None
+        arr[i].level = int(levels[i]) if levels is not None else 0
     return arr
 
 
 def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
-                stream=None):
+                stream=None, level=0):
     """Label a list of images with one launch per phase for the whole batch.
 
-    conn: int or per-image list.  num_components: optional device int32
-    tensor with one slot per image."""
+    conn, level: int or per-image list.  num_components: optional device
+    int32 tensor with one slot per image."""
     n = len(imgs)
     conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
+    levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
     if outs is None:
         outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
     counts = None
     if num_components is not None:
         counts = [num_components[i:i + 1] for i in range(n)]
-    arr = _descs(imgs, conns, outs, counts)
+    arr = _descs(imgs, conns, outs, counts, levels)
     _check(_lib.ccl_label_batch(arr, n, int(tile), _stream_handle(stream)))
     return outs
 
@@ -185,14 +199,16 @@ class BatchGraph:
     replayed with one launch.  The image and label tensors are kept alive and
     reused on every replay."""
 
-    def __init__(self, imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None):
+    def __init__(self, imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
+                 level=0):
         n = len(imgs)
         conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
+        levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
         if outs is None:
             outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
         counts = [num_components[i:i + 1] for i in range(n)] if num_components is not None else None
         self.imgs, self.outs, self.counts = list(imgs), outs, num_components
-        arr = _descs(imgs, conns, outs, counts)
+        arr = _descs(imgs, conns, outs, counts, levels)
         h = ctypes.c_void_p()
         _check(_lib.ccl_batch_graph_create(arr, n, int(tile), ctypes.byref(h)))
         self._h = h

@@ -85,6 +85,8 @@ int check_image(const void *img, int64_t H, int64_t W, int64_t stride, int conn,
     return CCL_OK;
 }
 
+int check_level(int level) { return (level < 0 || level > 255) ? CCL_ERR_LEVEL : CCL_OK; }
+
 int resolve_tile(int tile, TileCfg *out) {
     if (tile == 0)
         tile = 1;
@@ -159,6 +161,7 @@ Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     im.NTY = L.NTY;
     im.NTX = L.NTX;
     im.conn = d.conn;
+    im.level = d.level;
     im.nblk = L.nblk;
     return im;
 }
@@ -379,16 +382,23 @@ using namespace ccl;
 
 extern "C" {
 
-int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
-                 int32_t *num_components, int tile, hipStream_t stream) {
+int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
+                    int32_t *labels, int32_t *num_components, int tile, hipStream_t stream) {
     int st = check_image(img, H, W, stride, conn, labels);
     if (st != CCL_OK)
+        return st;
+    if ((st = check_level(level)) != CCL_OK)
         return st;
     TileCfg c;
     if ((st = resolve_tile(tile, &c)) != CCL_OK)
         return st;
-    ccl_image_desc d{img, H, W, stride, conn, labels, num_components};
+    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level};
     return run_batch(&d, 1, c, stream);
+}
+
+int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
+                 int32_t *num_components, int tile, hipStream_t stream) {
+    return ccl_label_level(img, H, W, stride, 0, conn, labels, num_components, tile, stream);
 }
 
 int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
@@ -407,6 +417,8 @@ int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t st
         return CCL_OK;
     for (int i = 0; i < n; i++) {
         st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
+        if (st == CCL_OK)
+            st = check_level(descs[i].level);
         if (st != CCL_OK)
             return st;
     }
@@ -421,7 +433,7 @@ size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile) {
     if (check_image(&dummy, H, W, W, conn, &dummy) != CCL_OK)
         return 0;
     ccl_image_desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy),
-                     nullptr};
+                     nullptr, 0};
     return batch_bytes(&d, 1, c, nullptr, nullptr);
 }
 
@@ -449,6 +461,8 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
         return st;
     for (int i = 0; i < n; i++) {
         st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
+        if (st == CCL_OK)
+            st = check_level(descs[i].level);
         if (st != CCL_OK)
             return st;
     }
@@ -608,6 +622,7 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_TILE: return "unknown tile configuration";
     case CCL_ERR_CAPTURE: return "workspace cannot grow while the stream is being captured (call ccl_reserve first)";
     case CCL_ERR_BATCH: return "invalid batch (n < 0 or descs NULL)";
+    case CCL_ERR_LEVEL: return "level must be in 0..255";
     default: return "unknown status";
     }
 }

@@ -63,6 +63,7 @@ struct Img {
     int32_t *blk;         // [nblk]      scan block totals -> exclusive scan
     int64_t stride;
     int32_t H, W, NTY, NTX, conn;
+    int32_t level;        // foreground iff byte > level (0..255; 0 = nonzero)
     int32_t tile0;        // first tile of this image in a batch-wide tile numbering
     int32_t edge0;        // first edge segment (boundary merge kernel)
     int32_t scan0;        // first scan block
@@ -245,32 +246,46 @@ __device__ __forceinline__ int popc_before(const uint32_t *row, int c) {
     return n + __popc(row[w] & mask_lt(c & 31));
 }
 
-// 4 bytes -> 4 bits (byte != 0).  The add sets bit 7 of every byte whose
-// low 7 bits are nonzero (no carry crosses a byte); OR-ing the byte covers
-// bit 7 itself.  The multiply gathers bits 7, 15, 23, 31 into bits 28..31.
-__device__ __forceinline__ uint32_t nz4(uint32_t x) {
-    uint32_t t = (((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u;
+// 4 bytes -> 4 bits (byte > level), for the foreground test.  With
+// level < 128: adding 127 - level to the low 7 bits of a byte sets its bit 7
+// iff those bits exceed level (no carry crosses a byte); OR-ing the byte adds
+// every byte >= 128.  With level >= 128 the byte needs bit 7 itself and low
+// bits above level - 128: add 255 - level and AND with the byte.  (level 0
+// is the plain nonzero test.)  The multiply gathers bits 7, 15, 23, 31 into
+// bits 28..31.
+template <bool HI>
+__device__ __forceinline__ uint32_t gt4(uint32_t x, uint32_t k) {
+    const uint32_t s = (x & 0x7f7f7f7fu) + k;
+    const uint32_t t = (HI ? (s & x) : (s | x)) & 0x80808080u;
     return (t * 0x00204081u) >> 28;
 }
 
-__device__ __forceinline__ uint32_t nz16(u32x4 v) {
-    return nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+template <bool HI>
+__device__ __forceinline__ uint32_t gt16(u32x4 v, uint32_t k) {
+    return gt4<HI>(v.x, k) | (gt4<HI>(v.y, k) << 4) | (gt4<HI>(v.z, k) << 8) | (gt4<HI>(v.w, k) << 12);
 }
 
-// 32 pixels of row y starting at column x (x % 32 == 0); outside = 0.
+// 32 pixels of row y starting at column x (x % 32 == 0), foreground iff the
+// byte exceeds the image's level; outside = 0.
 __device__ __forceinline__ uint32_t load_word(const Img &im, int y, int x) {
     if (y >= im.H || x >= im.W)
         return 0u;
     const uint8_t *p = im.img + (int64_t)y * im.stride + x;
+    const int lv = im.level;
     if (x + 32 <= im.W && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
         u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
         u32x4 b = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + 16));
-        return nz16(a) | (nz16(b) << 16);
+        if (lv < 128) {
+            const uint32_t k = (uint32_t)(127 - lv) * 0x01010101u;
+            return gt16<false>(a, k) | (gt16<false>(b, k) << 16);
+        }
+        const uint32_t k = (uint32_t)(255 - lv) * 0x01010101u;
+        return gt16<true>(a, k) | (gt16<true>(b, k) << 16);
     }
     uint32_t m = 0;
     int n = im.W - x < 32 ? im.W - x : 32;
     for (int i = 0; i < n; i++)
-        m |= (uint32_t)(p[i] != 0) << i;
+        m |= (uint32_t)((int)p[i] > lv) << i;
     return m;
 }
 

@@ -60,6 +60,15 @@ def test_status_codes_on_host():
         arr[i].conn = 8
     arr[1].conn = 5
     assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_CONN"]
+    arr[1].conn = 4
+    arr[0].level = 256
+    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_LEVEL"]
+    arr[0].level = -1
+    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_LEVEL"]
+    assert lib.ccl_label_level(dummy, 10, 10, 10, 256, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
+    assert lib.ccl_label_level(dummy, 10, 10, 10, -3, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
+    arr[0].level = 0
+    arr[1].conn = 5
     # graph creation validates the same way before allocating anything
     h = ctypes.c_void_p()
     assert lib.ccl_batch_graph_create(arr, 2, 0, ctypes.byref(h)) == S["CCL_ERR_CONN"] and not h.value
@@ -104,3 +113,17 @@ def test_product_path_is_independent_of_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, flags=re.M), f
                 assert "ccl_oracle" not in text, f
+
+
+def test_level_of_matches_the_fractional_threshold():
+    """level_of(f) must reproduce "v > f * 255" exactly for every byte v
+    (exact rational arithmetic), e.g. f = 0.5 -> foreground iff v >= 128."""
+    from fractions import Fraction
+
+    from paper_1606_05973_amd import ccl
+    for num in range(0, 1001):
+        f = Fraction(num, 1000)
+        lv = ccl.level_of(float(f))
+        for v in range(256):
+            assert (v > lv) == (v > f * 255), (num, v, lv)
+    assert ccl.level_of(0.5) == 127

@@ -174,3 +174,48 @@ def test_full_20000_adversarial(ccl, name):
             assert k == 1
         if name == "checkerboard":
             assert k == (1 if conn == 8 else 20000 * 20000 // 2)
+
+
+# ---------------------------------------------------------- fused threshold
+@pytest.mark.parametrize("conn", [8, 4])
+def test_threshold_levels(ccl, conn):
+    """Binarization fused into the image read: foreground iff byte > level,
+    against the oracle on the binarized image, on aligned, odd-width and
+    strided grayscale images, for levels across both halves of the range."""
+    g = inputs.gray(517, 777, 3.0, seed=9, device=DEV)
+    base = inputs.gray(300, 1100, 1.5, seed=10, device=DEV)
+    strided = base[:, 5:1030]
+    host = {id(g): g.cpu().numpy(), id(strided): strided.cpu().numpy()}
+    for img in (g, strided):
+        for lv in (0, 1, 64, 127, 128, 129, 200, 254, 255):
+            say(f"case threshold level={lv} shape={tuple(img.shape)} conn={conn}")
+            k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+            got = ccl.label(img, conn, level=lv, num_components=k)
+            torch.cuda.synchronize()
+            ref, kref = oracle.cclremsp(oracle.binarize(host[id(img)], lv), conn)
+            assert np.array_equal(got.cpu().numpy(), ref), lv
+            assert int(k.item()) == kref
+
+
+def test_threshold_batch_per_image_levels(ccl):
+    imgs = [inputs.gray(200 + 37 * i, 300 + 11 * i, 2.0 + i, seed=i, device=DEV) for i in range(6)]
+    levels = [0, 90, 127, 128, 170, 250]
+    conns = [8, 4, 8, 4, 8, 4]
+    say("case threshold batch")
+    outs = ccl.label_batch(imgs, conns, level=levels)
+    torch.cuda.synchronize()
+    for img, o, lv, c in zip(imgs, outs, levels, conns):
+        ref = oracle.label(img.cpu().numpy(), c, level=lv)
+        assert np.array_equal(o.cpu().numpy(), ref), (lv, c)
+
+
+def test_threshold_full_size_im2bw(ccl):
+    """A paper-scale grayscale image thresholded at luminance 0.5 (level 127)."""
+    img = inputs.gray(16384, 16384, 6.0, seed=3, device=DEV)
+    say("case threshold 16384^2 level 127")
+    k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    got = ccl.label(img, 8, level=127, num_components=k)
+    torch.cuda.synchronize()
+    ref, kref = oracle.cclremsp(oracle.binarize(img.cpu().numpy(), 127), 8)
+    assert int(k.item()) == kref
+    assert np.array_equal(got.cpu().numpy(), ref)

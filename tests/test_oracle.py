@@ -370,3 +370,24 @@ def test_planted_mistakes_are_caught(tmp_path, i):
         if caught:
             break
     assert caught, f"mutant {i} survived the exhaustive pin"
+
+
+def test_binarize_pins():
+    """Section V thresholding: foreground iff byte > level, checked against
+    every (byte, level) pair; level 0 is the nonzero test and level 255
+    leaves nothing; thresholding then labeling equals labeling a 0/1 image
+    built by hand."""
+    v = np.arange(256, dtype=np.uint8)
+    for lv in range(256):
+        b = oracle.binarize(v[None, :], lv)[0]
+        assert b.dtype == np.uint8
+        assert [int(x) for x in b] == [1 if x > lv else 0 for x in range(256)]
+    img = np.array([[0, 200, 90], [130, 127, 128], [255, 1, 0]], dtype=np.uint8)
+    # level 127 (a 0.5 luminance threshold): 128, 130, 200, 255 are foreground
+    assert oracle.binarize(img, 127).tolist() == [[0, 1, 0], [1, 0, 1], [1, 0, 0]]
+    lab = oracle.label(img, 8, level=127)
+    assert lab.tolist() == [[0, 1, 0], [1, 0, 1], [1, 0, 0]]
+    lab4 = oracle.label(img, 4, level=127)
+    assert lab4.tolist() == [[0, 1, 0], [2, 0, 3], [2, 0, 0]]
+    assert oracle.label(img, 8, level=0).tolist() == oracle.label((img > 0).astype(np.uint8), 8).tolist()
+    assert oracle.label(img, 8, level=255).max() == 0
