@@ -204,9 +204,13 @@ def main():
     ap.add_argument("--pitch", type=int, default=0,
                     help="image row pitch in bytes (0 = W); e.g. 256 rounds rows up to 256-byte alignment")
     ap.add_argument("--conn", type=int, default=8)
+    ap.add_argument("--scan", choices=["pair", "row"], default="pair",
+                    help="tile-local scan: runs of row pairs (default, 8-conn) or of single rows")
     ap.add_argument("--tile", type=int, default=0, help="tile configuration id (0 = default)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--ablation-steps", type=int, default=5,
+                    help="steps of the one-row vs two-row scan comparison (0 = skip)")
     ap.add_argument("--batch", type=int, default=256, help="images in the batched measurement (0 = skip)")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--serve-rates", default="1000,5000,10000,20000",
@@ -241,11 +245,12 @@ def main():
         content = f"Bernoulli p={args.p} seed 0"
     out = torch.empty((S, S), dtype=torch.int32, device=dev)
     kdev = torch.zeros(1, dtype=torch.int32, device=dev)
-    ccl.reserve(ccl.workspace_bytes(S, S, args.conn, args.tile))
-    th, tw = ccl.tile_shape(args.tile, args.conn)
+    scan = ccl.SCAN_ROW if args.scan == "row" else ccl.SCAN_PAIR
+    ccl.reserve(ccl.workspace_bytes(S, S, args.conn, args.tile, scan))
+    th, tw = ccl.tile_shape(args.tile, args.conn, scan)
 
     for _ in range(args.warmup):
-        ccl.label(img, args.conn, out=out, tile=args.tile, level=level)
+        ccl.label(img, args.conn, out=out, tile=args.tile, level=level, scan=scan)
     torch.cuda.synchronize()
 
     ccl.profile(True)
@@ -256,7 +261,7 @@ def main():
     t0 = time.perf_counter()
     start.record()
     for _ in range(args.steps):
-        ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kdev, level=level)
+        ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kdev, level=level, scan=scan)
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -280,7 +285,8 @@ def main():
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     workload_key = {"bernoulli": f"bernoulli{args.p}", "grf": f"grf{args.sigma}_{args.q}",
                     "gray": f"gray{args.sigma}_level{level}"}[args.content] + \
-        f"_{S}x{S}_conn{args.conn}_tile{th}x{tw}" + (f"_pitch{stride}" if stride != S else "")
+        f"_{S}x{S}_conn{args.conn}_tile{th}x{tw}" + (f"_pitch{stride}" if stride != S else "") + \
+        ("_scanrow" if args.scan == "row" else "")
     traffic = load_traffic(dom, workload_key)
 
     record = {
@@ -300,7 +306,7 @@ def main():
             "workload": f"{S}x{S} uint8 {content}, {args.conn}-connectivity, canonical int32 labels"
                         + (f", foreground iff byte > {level}" if level else ""),
             "H": S, "W": S, "stride": stride, "conn": args.conn, "tile": [th, tw], "parallelism": "single GPU",
-            "level": level,
+            "level": level, "scan": args.scan,
         },
         "roofline": {
             "bound": "hbm",
@@ -344,6 +350,20 @@ def main():
         if not args.no_verify:
             record["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), ref)) and int(kdev.item()) == kref
 
+    if args.ablation_steps > 0 and args.conn == 8:
+        # the paper's scan comparison (Table II) inside a tile: one-row runs
+        # vs two-row runs, same image, same everything else
+        other = ccl.SCAN_ROW if scan == ccl.SCAN_PAIR else ccl.SCAN_PAIR
+        ccl.reserve(ccl.workspace_bytes(S, S, 8, args.tile, other))
+        ccl.label(img, 8, out=out, tile=args.tile, level=level, scan=other)
+        t_other = _median_ms(torch, lambda: ccl.label(img, 8, out=out, tile=args.tile, level=level, scan=other),
+                             args.ablation_steps)
+        t_this = _median_ms(torch, lambda: ccl.label(img, 8, out=out, tile=args.tile, level=level, scan=scan),
+                            args.ablation_steps)
+        pair_ms, row_ms = (t_this, t_other) if scan == ccl.SCAN_PAIR else (t_other, t_this)
+        record["scan_ablation"] = {"pair_rows_ms": round(pair_ms, 4), "single_rows_ms": round(row_ms, 4),
+                                   "pair_speedup": round(row_ms / pair_ms, 3)}
+        log(f"scan ablation: pair {pair_ms:.3f} ms, row {row_ms:.3f} ms")
     del out, img
     torch.cuda.empty_cache()
     ccl.release()

@@ -47,8 +47,24 @@ typedef enum {
     CCL_ERR_TILE = -8,      /* unknown tile configuration id                    */
     CCL_ERR_CAPTURE = -9,   /* workspace must grow while the stream is captured */
     CCL_ERR_BATCH = -10,    /* n < 0, or descs NULL with n > 0                  */
-    CCL_ERR_LEVEL = -11     /* threshold level outside 0..255                   */
+    CCL_ERR_LEVEL = -11,    /* threshold level outside 0..255                   */
+    CCL_ERR_SCAN = -12      /* unknown scan strategy                            */
 } ccl_status;
+
+/*
+ * Tile-local scan strategy (the comparison of Table II, redone inside a
+ * tile).  Nodes of the tile-local union-find are runs of foreground pixels:
+ *   CCL_SCAN_PAIR  runs of the OR of two image rows (8-connectivity only):
+ *                  the two-row scan mask of ARemSP (Fig. 1b, Algorithm 6),
+ *                  which visits two rows per step; under 8-connectivity any
+ *                  two horizontally adjacent columns of a row pair that both
+ *                  hold foreground are connected, so such a run is one piece.
+ *                  The default; under 4-connectivity it means CCL_SCAN_ROW.
+ *   CCL_SCAN_ROW   runs of single rows, the one-row scan of CCLRemSP
+ *                  (Algorithm 4's mask); diagonal contacts are unions.
+ * Both give the same labels.
+ */
+typedef enum { CCL_SCAN_PAIR = 0, CCL_SCAN_ROW = 1 } ccl_scan;
 
 /*
  * ccl_label -- label one image (the whole two-pass method of Section III/IV:
@@ -105,6 +121,7 @@ typedef struct {
     int32_t *labels;         /* device, dense H x W */
     int32_t *num_components; /* device or NULL */
     int level;               /* foreground iff byte > level; 0 = nonzero */
+    int scan;                /* ccl_scan; 0 = CCL_SCAN_PAIR */
 } ccl_image_desc;
 
 /*

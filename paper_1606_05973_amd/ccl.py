@@ -29,7 +29,7 @@ class ImageDesc(ctypes.Structure):
     """ccl_image_desc of include/ccl.h."""
     _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
                 ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p),
-                ("level", ctypes.c_int)]
+                ("level", ctypes.c_int), ("scan", ctypes.c_int)]
 
 
 _lib.ccl_label.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _stream]
@@ -71,8 +71,9 @@ CCL_OK = 0
 STATUS = {
     "CCL_ERR_NULL": -1, "CCL_ERR_SHAPE": -2, "CCL_ERR_STRIDE": -3, "CCL_ERR_CONN": -4,
     "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
-    "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11,
+    "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11, "CCL_ERR_SCAN": -12,
 }
+SCAN_PAIR, SCAN_ROW = 0, 1   # ccl_scan: two-row (default) / one-row tile-local scan
 
 
 class CCLError(RuntimeError):
@@ -131,9 +132,14 @@ def level_of(fraction: float) -> int:
 
 
 def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
-          num_components: torch.Tensor | None = None, stream=None, level: int = 0) -> torch.Tensor:
+          num_components: torch.Tensor | None = None, stream=None, level: int = 0,
+          scan: int = SCAN_PAIR) -> torch.Tensor:
     """Canonical int32 labels of a 2-D uint8 device image; foreground iff the
-    byte exceeds `level` (0 = nonzero)."""
+    byte exceeds `level` (0 = nonzero).  `scan` picks the tile-local scan
+    strategy (SCAN_PAIR or SCAN_ROW); the labels do not depend on it."""
+    if scan != SCAN_PAIR:
+        return label_batch([img], conn, outs=None if out is None else [out], tile=tile,
+                           num_components=num_components, stream=stream, level=level, scan=scan)[0]
     H, W, stride = _img_geometry(img)
     if out is None:
         out = torch.empty((H, W), dtype=torch.int32, device=img.device)
@@ -155,7 +161,7 @@ def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: 
     return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
 
 
-def _descs(imgs, conns, outs, counts, levels=None):
+def _descs(imgs, conns, outs, counts, levels=None, scans=None):
     n = len(imgs)
     arr = (ImageDesc * max(n, 1))()
     for i, img in enumerate(imgs):
@@ -166,32 +172,34 @@ def _descs(imgs, conns, outs, counts, levels=None):
         arr[i].labels = outs[i].data_ptr()
         arr[i].num_components = counts[i].data_ptr() if counts is not None else None
         arr[i].level = int(levels[i]) if levels is not None else 0
+        arr[i].scan = int(scans[i]) if scans is not None else 0
     return arr
 
 
 def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
-                stream=None, level=0):
+                stream=None, level=0, scan=SCAN_PAIR):
     """Label a list of images with one launch per phase for the whole batch.
 
-    conn, level: int or per-image list.  num_components: optional device
-    int32 tensor with one slot per image."""
+    conn, level, scan: int or per-image list.  num_components: optional
+    device int32 tensor with one slot per image."""
     n = len(imgs)
     conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
     levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
+    scans = list(scan) if isinstance(scan, (list, tuple)) else [scan] * n
     if outs is None:
         outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
     counts = None
     if num_components is not None:
         counts = [num_components[i:i + 1] for i in range(n)]
-    arr = _descs(imgs, conns, outs, counts, levels)
+    arr = _descs(imgs, conns, outs, counts, levels, scans)
     _check(_lib.ccl_label_batch(arr, n, int(tile), _stream_handle(stream)))
     return outs
 
 
-def tile_shape(tile: int, conn: int):
+def tile_shape(tile: int, conn: int, scan: int = SCAN_PAIR):
     """(tile height, tile width) in pixels of configuration `tile` for `conn`."""
     nsr, tw = tile_configs()[max(tile, 1) - 1]
-    return nsr * (2 if conn == 8 else 1), tw
+    return nsr * (2 if conn == 8 and scan == SCAN_PAIR else 1), tw
 
 
 class BatchGraph:
@@ -200,15 +208,16 @@ class BatchGraph:
     reused on every replay."""
 
     def __init__(self, imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
-                 level=0):
+                 level=0, scan=SCAN_PAIR):
         n = len(imgs)
         conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
         levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
+        scans = list(scan) if isinstance(scan, (list, tuple)) else [scan] * n
         if outs is None:
             outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
         counts = [num_components[i:i + 1] for i in range(n)] if num_components is not None else None
         self.imgs, self.outs, self.counts = list(imgs), outs, num_components
-        arr = _descs(imgs, conns, outs, counts, levels)
+        arr = _descs(imgs, conns, outs, counts, levels, scans)
         h = ctypes.c_void_p()
         _check(_lib.ccl_batch_graph_create(arr, n, int(tile), ctypes.byref(h)))
         self._h = h
@@ -229,11 +238,13 @@ class BatchGraph:
             pass
 
 
-def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0) -> int:
+def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0, scan: int = SCAN_PAIR) -> int:
+    if scan != SCAN_PAIR:
+        return batch_workspace_bytes([(H, W)], conn, tile, scan)
     return int(_lib.ccl_workspace_bytes(H, W, conn, tile))
 
 
-def batch_workspace_bytes(shapes, conn=8, tile: int = 0) -> int:
+def batch_workspace_bytes(shapes, conn=8, tile: int = 0, scan=SCAN_PAIR) -> int:
     n = len(shapes)
     arr = (ImageDesc * max(n, 1))()
     for i, (H, W) in enumerate(shapes):
@@ -241,6 +252,7 @@ def batch_workspace_bytes(shapes, conn=8, tile: int = 0) -> int:
         arr[i].labels = 1
         arr[i].H, arr[i].W, arr[i].stride = H, W, W
         arr[i].conn = conn if isinstance(conn, int) else conn[i]
+        arr[i].scan = scan if isinstance(scan, int) else scan[i]
     return int(_lib.ccl_batch_workspace_bytes(arr, n, int(tile)))
 
 

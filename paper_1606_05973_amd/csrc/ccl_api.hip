@@ -24,7 +24,10 @@ struct TileCfg {
 constexpr TileCfg kTiles[] = {{32, 256}, {16, 256}, {16, 512}, {64, 128}, {32, 128}, {8, 512}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-inline int bh_of(int conn) { return conn == 8 ? 2 : 1; }
+// Image rows per block row: two under 8-connectivity with the pair-row scan
+// (the default), one otherwise.
+inline int bh_of(int conn, int scan) { return (conn == 8 && scan == CCL_SCAN_PAIR) ? 2 : 1; }
+inline int bh_of(const ccl_image_desc &d) { return bh_of(d.conn, d.scan); }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
@@ -34,9 +37,9 @@ struct Layout {
     size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
-Layout layout_of(int64_t H, int64_t W, int conn, const TileCfg &c) {
+Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c) {
     Layout L{};
-    L.th = c.nsr * bh_of(conn);
+    L.th = c.nsr * bh;
     L.NTY = (int32_t)((H + L.th - 1) / L.th);
     L.NTX = (int32_t)((W + c.tw - 1) / c.tw);
     L.NT = L.NTY * L.NTX;
@@ -86,6 +89,12 @@ int check_image(const void *img, int64_t H, int64_t W, int64_t stride, int conn,
 }
 
 int check_level(int level) { return (level < 0 || level > 255) ? CCL_ERR_LEVEL : CCL_OK; }
+
+int check_opts(const ccl_image_desc &d) {
+    if (d.scan != CCL_SCAN_PAIR && d.scan != CCL_SCAN_ROW)
+        return CCL_ERR_SCAN;
+    return check_level(d.level);
+}
 
 int resolve_tile(int tile, TileCfg *out) {
     if (tile == 0)
@@ -318,7 +327,7 @@ size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::ve
                    std::vector<size_t> *offs) {
     size_t off = align_up((size_t)n * sizeof(Img));
     for (int i = 0; i < n; i++) {
-        Layout L = layout_of(descs[i].H, descs[i].W, descs[i].conn, c);
+        Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), c);
         if (lays)
             lays->push_back(L);
         if (offs)
@@ -337,14 +346,14 @@ int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t 
     if (st != CCL_OK)
         return st;
     char *base = static_cast<char *>(ws);
-    std::vector<int> g8, g4;
+    std::vector<int> g2, g1;  // by image rows per block row
     for (int i = 0; i < n; i++)
-        (descs[i].conn == 8 ? g8 : g4).push_back(i);
+        (bh_of(descs[i]) == 2 ? g2 : g1).push_back(i);
     Img *dtab = reinterpret_cast<Img *>(base);
-    st = run_group(descs, g8, lays, offs, base, dtab, 2, c, stream);
+    st = run_group(descs, g2, lays, offs, base, dtab, 2, c, stream);
     if (st != CCL_OK)
         return st;
-    return run_group(descs, g4, lays, offs, base, dtab + g8.size(), 1, c, stream);
+    return run_group(descs, g1, lays, offs, base, dtab + g2.size(), 1, c, stream);
 }
 
 // Device table of one group, uploaded synchronously (used before capture).
@@ -392,7 +401,7 @@ int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, in
     TileCfg c;
     if ((st = resolve_tile(tile, &c)) != CCL_OK)
         return st;
-    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level};
+    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR};
     return run_batch(&d, 1, c, stream);
 }
 
@@ -418,7 +427,7 @@ int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t st
     for (int i = 0; i < n; i++) {
         st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
         if (st == CCL_OK)
-            st = check_level(descs[i].level);
+            st = check_opts(descs[i]);
         if (st != CCL_OK)
             return st;
     }
@@ -433,7 +442,7 @@ size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile) {
     if (check_image(&dummy, H, W, W, conn, &dummy) != CCL_OK)
         return 0;
     ccl_image_desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy),
-                     nullptr, 0};
+                     nullptr, 0, CCL_SCAN_PAIR};
     return batch_bytes(&d, 1, c, nullptr, nullptr);
 }
 
@@ -443,7 +452,8 @@ size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile) {
         return 0;
     for (int i = 0; i < n; i++) {
         int8_t dummy;
-        if (check_image(&dummy, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, &dummy) != CCL_OK)
+        if (check_image(&dummy, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, &dummy) != CCL_OK ||
+            check_opts(descs[i]) != CCL_OK)
             return 0;
     }
     return batch_bytes(descs, n, c, nullptr, nullptr);
@@ -462,7 +472,7 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
     for (int i = 0; i < n; i++) {
         st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
         if (st == CCL_OK)
-            st = check_level(descs[i].level);
+            st = check_opts(descs[i]);
         if (st != CCL_OK)
             return st;
     }
@@ -476,9 +486,9 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
         return CCL_ERR_NOMEM;
     }
     char *base = static_cast<char *>(g->ws);
-    std::vector<int> g8, g4;
+    std::vector<int> g8, g4;  // by image rows per block row (2, 1)
     for (int i = 0; i < n; i++)
-        (descs[i].conn == 8 ? g8 : g4).push_back(i);
+        (bh_of(descs[i]) == 2 ? g8 : g4).push_back(i);
     Img *dtab = reinterpret_cast<Img *>(base);
     st = upload_group_table(descs, g8, lays, offs, base, dtab);
     if (st == CCL_OK)
@@ -623,6 +633,7 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_CAPTURE: return "workspace cannot grow while the stream is being captured (call ccl_reserve first)";
     case CCL_ERR_BATCH: return "invalid batch (n < 0 or descs NULL)";
     case CCL_ERR_LEVEL: return "level must be in 0..255";
+    case CCL_ERR_SCAN: return "unknown scan strategy";
     default: return "unknown status";
     }
 }

@@ -439,7 +439,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     const int ty = ti / im.NTX, tx = ti % im.NTX;
     const int y0 = ty * TH, x0 = tx * TW;
     const int tid = threadIdx.x;
-    const bool conn8 = BH == 2;
+    const bool conn8 = im.conn == 8;
 
     // 1. foreground masks (kept in LDS; stored for the labeling pass at the
     // end, so that no barrier waits on those stores)
@@ -827,7 +827,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     const int32_t nH = (im.NTY - 1) * nxs, nV = (im.NTX - 1) * nys;
     if (e < 0 || e >= nH + nV)
         return;
-    const bool conn8 = BH == 2;
+    const bool conn8 = im.conn == 8;
     const uint16_t *lo, *hi;   // lo: the line of the later tiles, hi: of the earlier ones
     int from, n, later_t, period;
     const bool horiz = e < nH;

@@ -68,6 +68,9 @@ def test_status_codes_on_host():
     assert lib.ccl_label_level(dummy, 10, 10, 10, 256, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
     assert lib.ccl_label_level(dummy, 10, 10, 10, -3, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
     arr[0].level = 0
+    arr[1].scan = 2
+    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_SCAN"]
+    arr[1].scan = 0
     arr[1].conn = 5
     # graph creation validates the same way before allocating anything
     h = ctypes.c_void_p()
@@ -102,6 +105,9 @@ def test_workspace_bytes():
     assert ccl.workspace_bytes(21568, 21568, conn=4) < 5 * 21568 * 21568
     both = ccl.batch_workspace_bytes([(1000, 1000), (2000, 2000)])
     assert both >= a + b - 1024
+    # the one-row scan under 8-connectivity tiles like 4-connectivity
+    assert ccl.workspace_bytes(1000, 1000, 8, scan=ccl.SCAN_ROW) == ccl.workspace_bytes(1000, 1000, 4)
+    assert ccl.workspace_bytes(1000, 1000, 8, scan=7) == 0
 
 
 def test_product_path_is_independent_of_the_oracle():

@@ -219,3 +219,39 @@ def test_threshold_full_size_im2bw(ccl):
     ref, kref = oracle.cclremsp(oracle.binarize(img.cpu().numpy(), 127), 8)
     assert int(k.item()) == kref
     assert np.array_equal(got.cpu().numpy(), ref)
+
+
+# ------------------------------------------------------ scan strategy (rows)
+@pytest.mark.parametrize("tile", [0, 3, 6])
+def test_one_row_scan_8conn(ccl, tile):
+    """The one-row tile scan (runs of single rows, diagonal contacts as
+    unions) gives the same labels as the oracle under 8-connectivity."""
+    cases = [inputs.bernoulli(H, W, p, seed=H + W, device=DEV)
+             for (H, W) in [(1, 300), (31, 255), (65, 513), (999, 1000)] for p in (0.1, 0.5, 0.9)]
+    cases.append(inputs.grf(777, 1111, 6.0, 0.4, seed=4, device=DEV))
+    cases += [inputs.adversarial(n, 700, 900, device=DEV) for n in inputs.ADVERSARIAL]
+    for img in cases:
+        say(f"case scan=row tile={tile} shape={tuple(img.shape)}")
+        k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+        got = ccl.label(img, 8, tile=tile, num_components=k, scan=ccl.SCAN_ROW)
+        torch.cuda.synchronize()
+        ref, kref = oracle.cclremsp(img.cpu().numpy(), 8)
+        assert np.array_equal(got.cpu().numpy(), ref)
+        assert int(k.item()) == kref
+
+
+def test_one_row_scan_batch_and_full_size(ccl):
+    specs = inputs.batch_specs(10, seed=3, max_side=600)
+    imgs = [inputs.make(s_, device=DEV) for s_ in specs]
+    scans = [ccl.SCAN_ROW if i % 2 else ccl.SCAN_PAIR for i in range(len(imgs))]
+    conns = [8, 8, 4, 8, 8, 4, 8, 8, 4, 8]
+    say("case scan mix batch")
+    outs = ccl.label_batch(imgs, conns, scan=scans)
+    torch.cuda.synchronize()
+    for img, o, c in zip(imgs, outs, conns):
+        assert np.array_equal(o.cpu().numpy(), oracle.label(img.cpu().numpy(), c))
+    img = inputs.bernoulli(21568, 21568, 0.5, seed=0, device=DEV)
+    say("case scan=row 21568^2")
+    got = ccl.label(img, 8, scan=ccl.SCAN_ROW)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.label(img.cpu().numpy(), 8))
