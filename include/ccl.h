@@ -48,7 +48,9 @@ typedef enum {
     CCL_ERR_CAPTURE = -9,   /* workspace must grow while the stream is captured */
     CCL_ERR_BATCH = -10,    /* n < 0, or descs NULL with n > 0                  */
     CCL_ERR_LEVEL = -11,    /* threshold level outside 0..255                   */
-    CCL_ERR_SCAN = -12      /* unknown scan strategy                            */
+    CCL_ERR_SCAN = -12,     /* unknown scan strategy                            */
+    CCL_ERR_BUDGET = -13,   /* request needs more workspace than a server slot  */
+    CCL_ERR_TICKET = -14    /* unknown server ticket                            */
 } ccl_status;
 
 /*
@@ -194,6 +196,69 @@ int ccl_profile_read(double *ms, int nphase, int *ncalls);
 
 /* Static description of a status code. */
 const char *ccl_strerror(int status);
+
+/*
+ * Continuous-batching server.  Labeling requests (one image each, described
+ * as for ccl_label_batch) arrive at any time from any thread.  A scheduler
+ * thread inside the library keeps up to n_streams batches in flight, each on
+ * its own HIP stream with its own workspace of hbm_budget / n_streams bytes:
+ * whenever a stream's batch has completed, the requests waiting at that
+ * moment (in arrival order, up to max_batch images, max_batch_pixels pixels
+ * and the slot's workspace) are launched together as one batch, so requests
+ * that arrive while others are on the GPU join the next batch and batches on
+ * different streams overlap on the device.  Admission is by HBM footprint:
+ * a request is admitted into a batch only if its workspace region fits the
+ * free slot's workspace; one that could never fit is refused at submission
+ * with CCL_ERR_BUDGET.  Each result equals that of ccl_label_batch on the
+ * image alone (labels do not depend on batching).
+ *
+ * The workspaces are allocated once, at creation, on the current device;
+ * the images and label buffers belong to the caller and must stay valid
+ * until their request has completed.
+ */
+typedef struct ccl_server ccl_server;
+
+typedef struct {
+    int n_streams;              /* batches in flight at once, >= 1 */
+    int max_batch;              /* images per batch, >= 1 */
+    int64_t max_batch_pixels;   /* pixels per batch (a larger single image still runs alone) */
+    size_t hbm_budget;          /* device bytes of all slot workspaces together */
+    int tile;                   /* tile configuration id (0 = default) */
+} ccl_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected, batches, in_flight_max;
+    double pixels_completed;
+    double p50_ms, p99_ms, mean_ms;  /* submission-to-completion latency of completed requests */
+} ccl_server_stats;
+
+/* Create a server on the current device (CCL_ERR_BATCH for a config value
+ * out of range, CCL_ERR_NOMEM if the workspaces cannot be allocated). */
+int ccl_server_create(const ccl_server_config *cfg, ccl_server **out);
+
+/* Queue one request.  `ready`: a stream whose work so far must finish before
+ * the image is read and the labels written (e.g. the stream that produced
+ * the image), or NULL if the buffers are ready now.  *ticket identifies the
+ * request (> 0).  Argument errors as for ccl_label_batch; CCL_ERR_BUDGET if
+ * the image can never fit a slot. */
+int ccl_server_submit(ccl_server *s, const ccl_image_desc *d, hipStream_t ready, uint64_t *ticket);
+
+/* 1 if the request has completed (*latency_ms, if not NULL, gets its
+ * submission-to-completion time), 0 if not yet, CCL_ERR_TICKET if unknown. */
+int ccl_server_poll(ccl_server *s, uint64_t ticket, double *latency_ms);
+
+/* Block until the request has completed; returns CCL_OK or the first
+ * failure the scheduler met. */
+int ccl_server_wait(ccl_server *s, uint64_t ticket, double *latency_ms);
+
+/* Block until every submitted request has completed. */
+int ccl_server_drain(ccl_server *s);
+
+/* Counters and latency percentiles since creation. */
+int ccl_server_stats_get(ccl_server *s, ccl_server_stats *out);
+
+/* Finish all queued requests, stop the scheduler and free the server. */
+int ccl_server_destroy(ccl_server *s);
 
 #ifdef __cplusplus
 }

@@ -64,6 +64,34 @@ _lib.ccl_profile.argtypes = [ctypes.c_int]
 _lib.ccl_profile.restype = ctypes.c_int
 _lib.ccl_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.ccl_profile_read.restype = ctypes.c_int
+class ServerConfig(ctypes.Structure):
+    """ccl_server_config of include/ccl.h."""
+    _fields_ = [("n_streams", ctypes.c_int), ("max_batch", ctypes.c_int), ("max_batch_pixels", _i64),
+                ("hbm_budget", ctypes.c_size_t), ("tile", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    """ccl_server_stats of include/ccl.h."""
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("batches", _i64),
+                ("in_flight_max", _i64), ("pixels_completed", ctypes.c_double), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double)]
+
+
+_lib.ccl_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
+_lib.ccl_server_create.restype = ctypes.c_int
+_lib.ccl_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(ImageDesc), _stream,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+_lib.ccl_server_submit.restype = ctypes.c_int
+_lib.ccl_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+_lib.ccl_server_poll.restype = ctypes.c_int
+_lib.ccl_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+_lib.ccl_server_wait.restype = ctypes.c_int
+_lib.ccl_server_drain.argtypes = [ctypes.c_void_p]
+_lib.ccl_server_drain.restype = ctypes.c_int
+_lib.ccl_server_stats_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServerStats)]
+_lib.ccl_server_stats_get.restype = ctypes.c_int
+_lib.ccl_server_destroy.argtypes = [ctypes.c_void_p]
+_lib.ccl_server_destroy.restype = ctypes.c_int
 _lib.ccl_strerror.argtypes = [ctypes.c_int]
 _lib.ccl_strerror.restype = ctypes.c_char_p
 
@@ -72,6 +100,7 @@ STATUS = {
     "CCL_ERR_NULL": -1, "CCL_ERR_SHAPE": -2, "CCL_ERR_STRIDE": -3, "CCL_ERR_CONN": -4,
     "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
     "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11, "CCL_ERR_SCAN": -12,
+    "CCL_ERR_BUDGET": -13, "CCL_ERR_TICKET": -14,
 }
 SCAN_PAIR, SCAN_ROW = 0, 1   # ccl_scan: two-row (default) / one-row tile-local scan
 

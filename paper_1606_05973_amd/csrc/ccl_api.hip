@@ -3,8 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
+#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -286,16 +291,19 @@ int dispatch(const TileCfg &c, int bh, const Batch &b, int64_t tiles, int64_t ed
     return CCL_ERR_TILE;
 }
 
-// Images of one connectivity share every launch; a batch mixing 4- and
-// 8-connectivity runs as two such groups, one after the other on the stream.
-// Workspace: [tables of both groups][per-image regions].
+// Images with the same rows per block row share every launch; a batch
+// mixing them runs as two such groups, one after the other on the stream.
+// Workspace: [tables of both groups][per-image regions].  The group's table
+// is built in `htab` (pinned host memory that stays untouched until the
+// stream has passed the copy) or, when htab is NULL, in a temporary.
 int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
               const std::vector<size_t> &offs, char *base, Img *dtab, int bh, const TileCfg &c,
-              hipStream_t stream, bool table_ready = false) {
+              hipStream_t stream, bool table_ready = false, Img *htab = nullptr) {
     const int n = (int)idx.size();
     if (n == 0)
         return CCL_OK;
-    std::vector<Img> tab(n);
+    std::vector<Img> local(htab ? 0 : n);
+    Img *tab = htab ? htab : local.data();
     int64_t tiles = 0, edges = 0, blocks = 0;
     for (int k = 0; k < n; k++) {
         const int i = idx[k];
@@ -316,7 +324,7 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
         b.tab = nullptr;
     } else {
         if (!table_ready &&
-            hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
+            hipMemcpyAsync(dtab, tab, (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
             return CCL_ERR_HIP;
         b.tab = dtab;
     }
@@ -337,23 +345,29 @@ size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::ve
     return off;
 }
 
-int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream) {
+// Launch a batch into a workspace of at least batch_bytes(descs) bytes.
+int run_batch_in(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream, char *base,
+                 Img *htab = nullptr) {
     std::vector<Layout> lays;
     std::vector<size_t> offs;
-    const size_t total = batch_bytes(descs, n, c, &lays, &offs);
-    void *ws = nullptr;
-    int st = get_workspace(stream, total, &ws);
-    if (st != CCL_OK)
-        return st;
-    char *base = static_cast<char *>(ws);
+    batch_bytes(descs, n, c, &lays, &offs);
     std::vector<int> g2, g1;  // by image rows per block row
     for (int i = 0; i < n; i++)
         (bh_of(descs[i]) == 2 ? g2 : g1).push_back(i);
     Img *dtab = reinterpret_cast<Img *>(base);
-    st = run_group(descs, g2, lays, offs, base, dtab, 2, c, stream);
+    int st = run_group(descs, g2, lays, offs, base, dtab, 2, c, stream, false, htab);
     if (st != CCL_OK)
         return st;
-    return run_group(descs, g1, lays, offs, base, dtab + g2.size(), 1, c, stream);
+    return run_group(descs, g1, lays, offs, base, dtab + g2.size(), 1, c, stream, false,
+                     htab ? htab + g2.size() : nullptr);
+}
+
+int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream) {
+    void *ws = nullptr;
+    int st = get_workspace(stream, batch_bytes(descs, n, c, nullptr, nullptr), &ws);
+    if (st != CCL_OK)
+        return st;
+    return run_batch_in(descs, n, c, stream, static_cast<char *>(ws));
 }
 
 // Device table of one group, uploaded synchronously (used before capture).
@@ -634,8 +648,341 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_BATCH: return "invalid batch (n < 0 or descs NULL)";
     case CCL_ERR_LEVEL: return "level must be in 0..255";
     case CCL_ERR_SCAN: return "unknown scan strategy";
+    case CCL_ERR_BUDGET: return "request needs more workspace than a server slot holds";
+    case CCL_ERR_TICKET: return "unknown server ticket";
     default: return "unknown status";
     }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- server
+// Continuous batching (see ccl_server_create in ccl.h).  One scheduler
+// thread per server owns the slots; submitters only touch the queue.
+namespace ccl {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServerReq {
+    ccl_image_desc d;
+    uint64_t ticket;
+    hipEvent_t ready;      // recorded on the submitter's stream, or NULL
+    size_t bytes;          // this image's workspace region
+    Clock::time_point t_submit;
+};
+
+struct ServerSlot {
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;      // device workspace of ws_bytes
+    Img *htab = nullptr;     // pinned host image table (max_batch entries)
+    hipEvent_t done = nullptr;
+    std::vector<ServerReq> batch;
+    bool busy = false;
+};
+
+}  // namespace
+}  // namespace ccl
+
+struct ccl_server {
+    int dev = 0;
+    ccl_server_config cfg{};
+    ccl::TileCfg tile{};
+    size_t ws_bytes = 0;
+    std::vector<ccl::ServerSlot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<ccl::ServerReq> pending;
+    std::unordered_set<uint64_t> outstanding;
+    std::vector<double> lat_ms;      // by ticket - 1; < 0 while not done
+    std::vector<hipEvent_t> ev_free;
+    uint64_t next_ticket = 1;
+    int64_t rejected = 0, batches = 0, in_flight_max = 0, completed = 0;
+    double px_done = 0;
+    bool stop = false;
+    int error = CCL_OK;              // first HIP failure seen by the scheduler
+    std::thread th;
+
+    size_t bytes_of(const ccl_image_desc &d) const {
+        return ccl::layout_of(d.H, d.W, ccl::bh_of(d), tile).bytes;
+    }
+
+    void finish(ccl::ServerSlot &sl, Clock::time_point now) {
+        for (auto &r : sl.batch) {
+            lat_ms[r.ticket - 1] = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
+            outstanding.erase(r.ticket);
+            px_done += (double)r.d.H * (double)r.d.W;
+            completed++;
+            if (r.ready)
+                ev_free.push_back(r.ready);
+        }
+        sl.batch.clear();
+        sl.busy = false;
+    }
+
+    // Take the longest queue prefix that fits one slot.
+    std::vector<ccl::ServerReq> take_batch() {
+        std::vector<ccl::ServerReq> b;
+        size_t used = 0;
+        int64_t px = 0;
+        while (!pending.empty() && (int)b.size() < cfg.max_batch) {
+            const ccl::ServerReq &r = pending.front();
+            const int64_t n = r.d.H * r.d.W;
+            const size_t need = ccl::align_up((b.size() + 1) * sizeof(ccl::Img)) + used + r.bytes;
+            if (!b.empty() && (px + n > cfg.max_batch_pixels || need > ws_bytes))
+                break;
+            used += r.bytes;
+            px += n;
+            b.push_back(r);
+            pending.pop_front();
+        }
+        return b;
+    }
+
+    void loop() {
+        (void)hipSetDevice(dev);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            int busy = 0;
+            for (auto &sl : slots) {
+                if (!sl.busy)
+                    continue;
+                const hipError_t q = hipEventQuery(sl.done);
+                if (q == hipSuccess) {
+                    finish(sl, Clock::now());
+                    cv_done.notify_all();
+                } else if (q != hipErrorNotReady) {
+                    if (error == CCL_OK)
+                        error = CCL_ERR_HIP;
+                    finish(sl, Clock::now());
+                    cv_done.notify_all();
+                } else {
+                    busy++;
+                }
+            }
+            for (auto &sl : slots) {
+                if (sl.busy || pending.empty())
+                    continue;
+                std::vector<ccl::ServerReq> b = take_batch();
+                lk.unlock();
+                std::vector<ccl_image_desc> descs;
+                int st = CCL_OK;
+                for (auto &r : b) {
+                    descs.push_back(r.d);
+                    if (r.ready && hipStreamWaitEvent(sl.stream, r.ready, 0) != hipSuccess)
+                        st = CCL_ERR_HIP;
+                }
+                if (st == CCL_OK)
+                    st = ccl::run_batch_in(descs.data(), (int)descs.size(), tile, sl.stream, sl.ws, sl.htab);
+                if (st == CCL_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess)
+                    st = CCL_ERR_HIP;
+                lk.lock();
+                sl.batch = std::move(b);
+                sl.busy = true;
+                batches++;
+                if (st != CCL_OK) {
+                    if (error == CCL_OK)
+                        error = st;
+                    finish(sl, Clock::now());
+                    cv_done.notify_all();
+                    continue;
+                }
+                busy++;
+                in_flight_max = std::max<int64_t>(in_flight_max, busy);
+            }
+            if (stop && pending.empty() && busy == 0)
+                return;
+            if (busy)
+                cv_work.wait_for(lk, std::chrono::microseconds(20));
+            else
+                cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        }
+    }
+};
+
+extern "C" {
+
+int ccl_server_create(const ccl_server_config *cfg, ccl_server **out) {
+    if (!cfg || !out)
+        return CCL_ERR_NULL;
+    *out = nullptr;
+    if (cfg->n_streams < 1 || cfg->max_batch < 1 || cfg->max_batch_pixels < 1 || cfg->hbm_budget == 0)
+        return CCL_ERR_BATCH;
+    ccl::TileCfg tc;
+    int st = ccl::resolve_tile(cfg->tile, &tc);
+    if (st != CCL_OK)
+        return st;
+    ccl_server *s = new ccl_server();
+    s->cfg = *cfg;
+    s->tile = tc;
+    s->ws_bytes = cfg->hbm_budget / (size_t)cfg->n_streams;
+    if (hipGetDevice(&s->dev) != hipSuccess) {
+        delete s;
+        return CCL_ERR_HIP;
+    }
+    s->slots.resize(cfg->n_streams);
+    for (auto &sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.htab), (size_t)cfg->max_batch * sizeof(ccl::Img)) !=
+                hipSuccess)
+            st = CCL_ERR_HIP;
+        else if (hipMalloc(reinterpret_cast<void **>(&sl.ws), s->ws_bytes) != hipSuccess)
+            st = CCL_ERR_NOMEM;
+        if (st != CCL_OK)
+            break;
+    }
+    if (st != CCL_OK) {
+        (void)hipGetLastError();
+        for (auto &sl : s->slots) {
+            if (sl.ws) (void)hipFree(sl.ws);
+            if (sl.htab) (void)hipHostFree(sl.htab);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
+        delete s;
+        return st;
+    }
+    s->th = std::thread([s] { s->loop(); });
+    *out = s;
+    return CCL_OK;
+}
+
+int ccl_server_submit(ccl_server *s, const ccl_image_desc *d, hipStream_t ready, uint64_t *ticket) {
+    if (!s || !d || !ticket)
+        return CCL_ERR_NULL;
+    int st = ccl::check_image(d->img, d->H, d->W, d->stride, d->conn, d->labels);
+    if (st == CCL_OK)
+        st = ccl::check_opts(*d);
+    if (st != CCL_OK)
+        return st;
+    ccl::ServerReq r{};
+    r.d = *d;
+    r.bytes = s->bytes_of(*d);
+    if (ccl::align_up(sizeof(ccl::Img)) + r.bytes > s->ws_bytes) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->rejected++;
+        return CCL_ERR_BUDGET;
+    }
+    r.ready = nullptr;
+    if (ready) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (!s->ev_free.empty()) {
+                r.ready = s->ev_free.back();
+                s->ev_free.pop_back();
+            }
+        }
+        if (!r.ready && hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess)
+            return CCL_ERR_HIP;
+        if (hipEventRecord(r.ready, ready) != hipSuccess) {
+            (void)hipEventDestroy(r.ready);
+            return CCL_ERR_HIP;
+        }
+    }
+    r.t_submit = ccl::Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            if (r.ready)
+                s->ev_free.push_back(r.ready);
+            return CCL_ERR_BATCH;
+        }
+        r.ticket = s->next_ticket++;
+        s->lat_ms.push_back(-1.0);
+        s->outstanding.insert(r.ticket);
+        s->pending.push_back(r);
+        *ticket = r.ticket;
+    }
+    s->cv_work.notify_one();
+    return CCL_OK;
+}
+
+int ccl_server_poll(ccl_server *s, uint64_t ticket, double *latency_ms) {
+    if (!s)
+        return CCL_ERR_NULL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (ticket == 0 || ticket >= s->next_ticket)
+        return CCL_ERR_TICKET;
+    if (s->outstanding.count(ticket))
+        return 0;
+    if (latency_ms)
+        *latency_ms = s->lat_ms[ticket - 1];
+    return 1;
+}
+
+int ccl_server_wait(ccl_server *s, uint64_t ticket, double *latency_ms) {
+    if (!s)
+        return CCL_ERR_NULL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (ticket == 0 || ticket >= s->next_ticket)
+        return CCL_ERR_TICKET;
+    s->cv_done.wait(lk, [&] { return !s->outstanding.count(ticket); });
+    if (latency_ms)
+        *latency_ms = s->lat_ms[ticket - 1];
+    return s->error;
+}
+
+int ccl_server_drain(ccl_server *s) {
+    if (!s)
+        return CCL_ERR_NULL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->outstanding.empty(); });
+    return s->error;
+}
+
+int ccl_server_stats_get(ccl_server *s, ccl_server_stats *out) {
+    if (!s || !out)
+        return CCL_ERR_NULL;
+    std::vector<double> lat;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        out->submitted = (int64_t)(s->next_ticket - 1);
+        out->completed = s->completed;
+        out->rejected = s->rejected;
+        out->batches = s->batches;
+        out->in_flight_max = s->in_flight_max;
+        out->pixels_completed = s->px_done;
+        for (double v : s->lat_ms)
+            if (v >= 0)
+                lat.push_back(v);
+    }
+    out->p50_ms = out->p99_ms = out->mean_ms = 0;
+    if (!lat.empty()) {
+        std::sort(lat.begin(), lat.end());
+        const size_t n = lat.size();
+        out->p50_ms = lat[std::min(n - 1, (size_t)(0.50 * n))];
+        out->p99_ms = lat[std::min(n - 1, (size_t)(0.99 * n))];
+        double sum = 0;
+        for (double v : lat)
+            sum += v;
+        out->mean_ms = sum / (double)n;
+    }
+    return s->error;
+}
+
+int ccl_server_destroy(ccl_server *s) {
+    if (!s)
+        return CCL_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->th.joinable())
+        s->th.join();
+    const int err = s->error;
+    for (auto &sl : s->slots) {
+        (void)hipStreamSynchronize(sl.stream);
+        (void)hipFree(sl.ws);
+        (void)hipHostFree(sl.htab);
+        (void)hipEventDestroy(sl.done);
+        (void)hipStreamDestroy(sl.stream);
+    }
+    for (hipEvent_t e : s->ev_free)
+        (void)hipEventDestroy(e);
+    delete s;
+    return err;
 }
 
 }  // extern "C"

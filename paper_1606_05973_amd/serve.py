@@ -1,17 +1,17 @@
-"""Continuous-batching labeling server.
+"""Continuous-batching labeling server: Python face of the library's native
+server (ccl_server_* in include/ccl.h).
 
-Requests (a device-resident uint8 image and a connectivity) arrive at any
-time.  A scheduler thread keeps up to `n_streams` batches in flight on their
-own HIP streams: whenever a stream is free and HBM allows, it admits the
-waiting requests into a new batch (one ccl_label_batch call), so requests
-that arrive while others are on the GPU join the next batch instead of
-waiting for the queue to drain, and batches on different streams overlap on
-the device.  Admission is by HBM footprint: each request needs its label
-buffer (4 B/px) and its share of the batch workspace
-(ccl_batch_workspace_bytes); the footprint of everything in flight stays
-under `hbm_budget` bytes, and a request that could never fit is rejected at
-submission.  Completion is detected with events; latency is measured from
-submission to the moment the scheduler sees the batch's event complete.
+Requests (a device-resident uint8 image, a connectivity, optionally a
+threshold level) arrive at any time.  The scheduler runs in the library, on
+its own thread, without the interpreter lock: it keeps up to `n_streams`
+batches in flight on their own HIP streams and, whenever one completes,
+launches the requests waiting at that moment as the next batch, so requests
+that arrive while others are on the GPU join the next batch and batches on
+different streams overlap on the device.  Admission is by HBM footprint: the
+server owns `hbm_budget` bytes of workspace split evenly over its streams, a
+request joins a batch only if its workspace region fits, and one that could
+never fit is rejected at submission.  Latency is measured by the library
+from submission to the moment the scheduler sees the batch complete.
 
 Each result is the same whether the image is labeled alone or in a mix:
 labels are canonical (components ranked by smallest raster index) and do
@@ -20,9 +20,7 @@ not depend on tiling, batching or scheduling.
 from __future__ import annotations
 
 import collections
-import statistics
-import threading
-import time
+import ctypes
 
 import torch
 
@@ -30,173 +28,136 @@ from . import ccl
 
 
 class Request:
-    __slots__ = ("rid", "img", "conn", "t_submit", "t_launch", "t_done", "labels", "status", "footprint", "_done")
+    """One submitted image.  `labels` is valid once `wait()` returned (or
+    `done` is true); `latency` is in seconds."""
 
-    def __init__(self, rid, img, conn):
-        self.rid = rid
-        self.img = img
-        self.conn = conn
-        self.t_submit = time.perf_counter()
-        self.t_launch = None
-        self.t_done = None
-        self.labels = None
-        self.status = "queued"
-        self.footprint = 0
-        self._done = threading.Event()
+    __slots__ = ("server", "rid", "img", "conn", "labels", "_status", "_lat")
 
-    def wait(self, timeout=None) -> bool:
-        return self._done.wait(timeout)
+    def __init__(self, server, rid, img, conn, labels, status):
+        self.server, self.rid, self.img, self.conn, self.labels = server, rid, img, conn, labels
+        self._status = status
+        self._lat = None
+
+    def _poll(self, block: bool):
+        if self._status != "queued":
+            return
+        lat = ctypes.c_double()
+        fn = ccl._lib.ccl_server_wait if block else ccl._lib.ccl_server_poll
+        st = fn(self.server._h, self.rid, ctypes.byref(lat))
+        if block:
+            ccl._check(st)
+            st = 1
+        elif st < 0:
+            ccl._check(st)
+        if st == 1:
+            self._status = "done"
+            self._lat = lat.value * 1e-3
+
+    def wait(self) -> bool:
+        self._poll(True)
+        return self._status == "done"
+
+    @property
+    def done(self) -> bool:
+        self._poll(False)
+        return self._status == "done"
+
+    @property
+    def status(self) -> str:
+        self._poll(False)
+        return self._status
 
     @property
     def latency(self):
-        return None if self.t_done is None else self.t_done - self.t_submit
+        self._poll(False)
+        return self._lat
 
 
 class Server:
     def __init__(self, hbm_budget: int = 8 << 30, n_streams: int = 3, max_batch: int = 64,
-                 max_batch_pixels: int = 96 << 20, tile: int = 0, device="cuda:0", on_done=None):
-        self.budget = int(hbm_budget)
-        self.on_done = on_done      # called with each finished Request, on the scheduler thread
-        self.max_batch = max_batch
-        self.max_batch_pixels = max_batch_pixels
-        self.tile = tile
+                 max_batch_pixels: int = 96 << 20, tile: int = 0, device="cuda:0"):
         self.device = torch.device(device)
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
-        # Grow each stream's library workspace once, up front, to what a full
-        # batch needs, so that serving never waits on a reallocation.
-        side = int(max_batch_pixels ** 0.5) + 1
-        ws = ccl.batch_workspace_bytes([(side, side)] * 2, 4, tile) + max_batch * (1 << 20)
+        cfg = ccl.ServerConfig(n_streams=n_streams, max_batch=max_batch, max_batch_pixels=max_batch_pixels,
+                               hbm_budget=int(hbm_budget), tile=tile)
+        h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            for st in self.streams:
-                ccl.reserve(ws, st)
-        self.free_streams = list(range(n_streams))
-        self.pending = collections.deque()
-        self.inflight = []          # (stream index, event, [requests], footprint)
-        self.used = 0               # bytes held by in-flight batches
-        self.lock = threading.Lock()
-        self.wake = threading.Event()
-        self.stop_flag = False
-        self.done = []
-        self.rejected = 0
-        self.batches = 0
-        self.max_inflight = 0
-        self._next_id = 0
-        self.thread = threading.Thread(target=self._loop, name="ccl-serve", daemon=True)
-        self.thread.start()
+            ccl._check(ccl._lib.ccl_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._final = None
+        # label buffers of requests not yet seen complete: kept referenced so
+        # that the allocator cannot hand their memory out while the GPU writes
+        self._inflight = collections.deque()
 
-    # ------------------------------------------------------------------ API
-    def request_footprint(self, H: int, W: int, conn: int) -> int:
-        return H * W * 4 + ccl.workspace_bytes(H, W, conn, self.tile)
-
-    def submit(self, img: torch.Tensor, conn: int = 8) -> Request:
-        with self.lock:
-            r = Request(self._next_id, img, conn)
-            self._next_id += 1
-        H, W = img.shape
-        r.footprint = self.request_footprint(H, W, conn)
-        if r.footprint > self.budget:
-            r.status = "rejected"
-            r.t_done = time.perf_counter()
-            with self.lock:
-                self.rejected += 1
-            r._done.set()
-            return r
-        with self.lock:
-            self.pending.append(r)
-        self.wake.set()
+    def submit(self, img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, level: int = 0,
+               scan: int = ccl.SCAN_PAIR) -> Request:
+        H, W, stride = ccl._img_geometry(img)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+        d = ccl.ImageDesc(img=img.data_ptr(), H=H, W=W, stride=stride, conn=int(conn), labels=out.data_ptr(),
+                          num_components=None, level=int(level), scan=int(scan))
+        t = ctypes.c_uint64()
+        # the image and label buffer are ready once the current stream's work is
+        st = ccl._lib.ccl_server_submit(self._h, ctypes.byref(d), ccl._stream_handle(None), ctypes.byref(t))
+        if st == ccl.STATUS["CCL_ERR_BUDGET"]:
+            return Request(self, 0, img, conn, None, "rejected")
+        ccl._check(st)
+        r = Request(self, t.value, img, conn, out, "queued")
+        self._inflight.append(r)
+        while self._inflight and self._inflight[0].done:
+            self._inflight.popleft()
         return r
 
+    def drain(self):
+        ccl._check(ccl._lib.ccl_server_drain(self._h))
+        for r in self._inflight:   # all complete now: record their latencies
+            r._poll(False)
+        self._inflight.clear()
+
     def close(self, drain: bool = True):
-        if drain:
-            while True:
-                with self.lock:
-                    if not self.pending and not self.inflight:
-                        break
-                time.sleep(1e-4)
-        self.stop_flag = True
-        self.wake.set()
-        self.thread.join()
+        if self._h:
+            if drain:
+                self.drain()
+            self._final = self._stats()
+            st = ccl._lib.ccl_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._inflight.clear()
+            ccl._check(st)
 
-    def stats(self, t0: float, t1: float):
-        lat = sorted(r.latency for r in self.done if r.status == "done")
-        px = sum(r.img.numel() for r in self.done if r.status == "done")
+    def _stats(self):
+        s = ccl.ServerStats()
+        ccl._check(ccl._lib.ccl_server_stats_get(self._h, ctypes.byref(s)))
+        return s
 
-        def pct(q):
-            return lat[min(len(lat) - 1, int(q * len(lat)))] * 1e3 if lat else None
-        return {
-            "completed": len(lat), "rejected": self.rejected, "batches": self.batches,
-            "max_batches_in_flight": self.max_inflight,
-            "p50_ms": pct(0.50), "p99_ms": pct(0.99), "mean_ms": statistics.mean(lat) * 1e3 if lat else None,
-            "gpx_per_s": px / max(t1 - t0, 1e-9) / 1e9,
+    def stats(self, t0: float | None = None, t1: float | None = None) -> dict:
+        """Counters and latency percentiles (ms) since creation (a closed
+        server reports its final ones); gpx_per_s over [t0, t1] seconds."""
+        s = self._stats() if self._h else self._final
+        out = {
+            "submitted": s.submitted, "completed": s.completed, "rejected": s.rejected, "batches": s.batches,
+            "max_batches_in_flight": s.in_flight_max, "p50_ms": s.p50_ms, "p99_ms": s.p99_ms,
+            "mean_ms": s.mean_ms, "pixels_completed": s.pixels_completed,
         }
+        if t0 is not None and t1 is not None:
+            out["gpx_per_s"] = s.pixels_completed / max(t1 - t0, 1e-9) / 1e9
+        return out
 
-    # ------------------------------------------------------------ scheduler
-    def _retire(self):
-        still = []
-        for si, ev, reqs, fp in self.inflight:
-            if ev.query():
-                now = time.perf_counter()
-                for r in reqs:
-                    r.t_done = now
-                    r.status = "done"
-                    r._done.set()
-                    if self.on_done is not None:
-                        self.on_done(r)
-                self.done.extend(reqs)
-                self.used -= fp
-                self.free_streams.append(si)
-            else:
-                still.append((si, ev, reqs, fp))
-        self.inflight = still
+    def latency_stats(self, first: int, last: int) -> dict:
+        """p50 / p99 / mean latency (ms) of the completed requests with
+        tickets first..last (the library keeps each request's latency)."""
+        lat = []
+        for t in range(first, last + 1):
+            v = ctypes.c_double()
+            if ccl._lib.ccl_server_poll(self._h, t, ctypes.byref(v)) == 1:
+                lat.append(v.value)
+        lat.sort()
+        n = len(lat)
+        if not n:
+            return {"p50_ms": None, "p99_ms": None, "mean_ms": None, "n": 0}
+        return {"p50_ms": lat[min(n - 1, int(0.5 * n))], "p99_ms": lat[min(n - 1, int(0.99 * n))],
+                "mean_ms": sum(lat) / n, "n": n}
 
-    def _admit(self) -> bool:
-        launched = False
-        while self.free_streams:
-            batch, fp, px = [], 0, 0
-            with self.lock:
-                while self.pending and len(batch) < self.max_batch:
-                    r = self.pending[0]
-                    n = r.img.numel()
-                    if batch and px + n > self.max_batch_pixels:
-                        break
-                    if self.used + fp + r.footprint > self.budget:
-                        break
-                    self.pending.popleft()
-                    batch.append(r)
-                    fp += r.footprint
-                    px += n
-            if not batch:
-                return launched
-            si = self.free_streams.pop()
-            s = self.streams[si]
-            with torch.cuda.stream(s):
-                outs = [torch.empty(tuple(r.img.shape), dtype=torch.int32, device=self.device) for r in batch]
-                now = time.perf_counter()
-                for r, o in zip(batch, outs):
-                    r.labels = o
-                    r.t_launch = now
-                    r.status = "running"
-                ccl.label_batch([r.img for r in batch], [r.conn for r in batch], outs=outs, tile=self.tile, stream=s)
-                ev = torch.cuda.Event()
-                ev.record(s)
-            self.used += fp
-            self.batches += 1
-            self.inflight.append((si, ev, batch, fp))
-            self.max_inflight = max(self.max_inflight, len(self.inflight))
-            launched = True
-        return launched
-
-    def _loop(self):
-        torch.cuda.set_device(self.device)
-        while True:
-            self._retire()
-            launched = self._admit()
-            with self.lock:
-                idle = not self.pending and not self.inflight
-            if self.stop_flag and idle:
-                return
-            if idle:
-                self.wake.wait(0.001)
-                self.wake.clear()
-            elif not launched:
-                time.sleep(20e-6)
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -93,16 +93,56 @@ def test_serve_alone_equals_mix(ccl):
             time.sleep(rng.random() * 0.002)
     huge = torch.zeros((12000, 12000), dtype=torch.uint8, device=DEV)
     rej = srv.submit(huge, 8)
-    srv.close()
+    srv.drain()
     t1 = time.perf_counter()
     st = srv.stats(t0, t1)
+    srv.close()
     say("serve stats", st)
     assert rej.status == "rejected" and st["rejected"] == 1
-    assert st["completed"] == 120
+    assert st["completed"] == 120 and st["submitted"] == 120
+    assert st["batches"] < 120  # requests were batched
+    assert srv.stats()["completed"] == 120  # final counters survive close
     for r in reqs:
-        assert r.status == "done"
+        assert r.status == "done" and r.latency is not None and r.latency > 0
         alone = ccl.label(r.img, r.conn)
         torch.cuda.synchronize()
         assert torch.equal(alone, r.labels), r.rid
     for r in reqs[:10]:
         assert np.array_equal(r.labels.cpu().numpy(), _oracle(r.img, r.conn)[0])
+
+
+def test_serve_waits_for_the_producing_stream(ccl):
+    """A request submitted while its image is still being written on the
+    current stream is labeled after that write (the ready stream)."""
+    from paper_1606_05973_amd import serve
+    srv = serve.Server(hbm_budget=128 << 20, n_streams=2, max_batch=4)
+    side = torch.cuda.Stream()
+    reqs, refs = [], []
+    for i in range(6):
+        src = inputs.bernoulli(400 + 50 * i, 500, 0.5, seed=40 + i, device=DEV)
+        torch.cuda.synchronize()
+        img = torch.zeros_like(src)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            torch.cuda._sleep(2_000_000)  # keep the stream busy before the copy
+            img.copy_(src)
+            reqs.append(srv.submit(img, 8, level=0))
+        refs.append(src)
+    for r, src in zip(reqs, refs):
+        assert r.wait()
+        torch.cuda.synchronize()
+        assert np.array_equal(r.labels.cpu().numpy(), _oracle(src, 8)[0])
+    srv.close()
+
+
+def test_serve_threshold_and_scan_options(ccl):
+    from paper_1606_05973_amd import serve
+    srv = serve.Server(hbm_budget=128 << 20, n_streams=2, max_batch=16)
+    imgs = [inputs.gray(300 + 13 * i, 400, 2.0, seed=i, device=DEV) for i in range(8)]
+    torch.cuda.synchronize()
+    reqs = [srv.submit(im, 8 if i % 2 else 4, level=60 + 20 * i, scan=i % 2) for i, im in enumerate(imgs)]
+    srv.drain()
+    for i, (im, r) in enumerate(zip(imgs, reqs)):
+        ref = oracle.label(im.cpu().numpy(), 8 if i % 2 else 4, level=60 + 20 * i)
+        assert np.array_equal(r.labels.cpu().numpy(), ref)
+    srv.close()
