@@ -20,6 +20,8 @@ merger_pairs(p, pairs)       -> p                       Algorithm 8 (sequential 
 flatten(p, count)            -> (p, K)                  Algorithm 3
 label(img, conn, level)      -> labels                  the reference labeling (CCLRemSP)
 binarize(img, level)         -> uint8 0/1               Section V thresholding
+gray(img, conn)              -> (labels, K)             gray-level extension (Section V):
+                                                        equal nonzero neighbours connect
 
 All labelings returned by ``cclremsp``, ``aremsp`` and ``paremsp`` use the
 canonical numbering: 0 is background and component k (1-based) is the k-th
@@ -66,6 +68,8 @@ def _load():
             lib.oracle_aremsp.restype = i64
             lib.oracle_paremsp.argtypes = [u8p, i64, i64, i64, ctypes.c_int, i32p, ctypes.c_int]
             lib.oracle_paremsp.restype = i64
+            lib.oracle_gray.argtypes = [u8p, i64, i64, i64, ctypes.c_int, i32p]
+            lib.oracle_gray.restype = i64
             lib.oracle_canonical.argtypes = [i32p, i64, i64]
             lib.oracle_canonical.restype = i64
             lib.oracle_merge_pairs.argtypes = [i32p, i32p, i64]
@@ -162,6 +166,20 @@ def flatten(p, count: int):
     p = np.ascontiguousarray(p, dtype=np.int32).copy()
     k = lib.oracle_flatten(_i32ptr(p), int(count))
     return p, int(k)
+
+
+def gray(img, conn: int = 8):
+    """Gray-level labeling (the extension Section V mentions): object pixels
+    are nonzero bytes, neighbouring object pixels connect when their bytes
+    are equal; canonical numbering."""
+    lib = _load()
+    img = np.asarray(img)
+    if img.dtype != np.uint8:
+        raise ValueError("gray labeling takes uint8 images")
+    img, ptr, H, W, stride = _img_args(img)
+    out = np.empty((H, W), dtype=np.int32)
+    k = lib.oracle_gray(ptr, H, W, stride, conn, _i32ptr(out))
+    return out, _check(k)
 
 
 def binarize(img, level: int):

@@ -18,6 +18,12 @@
  *   paremsp      -- PARemSP: chunked ARemSP scans with disjoint label
  *                   ranges, boundary-row merge with merger (Algorithms 7, 8)
  *                   executed one chunk after another, flatten, labeling
+ *   gray         -- the gray-level extension the paper mentions (Section V;
+ *                   the abstract's "adjacent pixels sharing the same
+ *                   features"): object pixels are the nonzero bytes and two
+ *                   neighbouring object pixels are connected when their
+ *                   bytes are equal; same raster scan with merge, flatten,
+ *                   labeling
  *   canonical    -- renumbers a labeling so that component k is the k-th
  *                   component met in raster order (the required output
  *                   numbering; not in the paper)
@@ -359,6 +365,48 @@ static int64_t canonical_numbering(int32_t *label, int64_t H, int64_t W, int32_t
     return next - 1;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Gray-level scan.  The already-scanned neighbours of e (a, b, c, d of     */
+/* Fig. 1a under 8-connectivity, b and d under 4) whose byte equals e's     */
+/* byte are merged with Algorithm 2; e takes a member of their united set,  */
+/* or a new label when none has e's value.  Labels are handed out in raster */
+/* order and every set's root is its smallest label, so the flatten         */
+/* numbering is canonical.  Returns the largest label handed out.           */
+/* ---------------------------------------------------------------------- */
+static int32_t scan_gray(const image_t *im, int conn, int32_t *label, int32_t *p)
+{
+    static const int nb8[4][2] = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}};
+    static const int nb4[2][2] = {{-1, 0}, {0, -1}};
+    const int (*nb)[2] = conn == 8 ? nb8 : nb4;
+    const int nn = conn == 8 ? 4 : 2;
+    int32_t count = 1;
+    p[0] = 0;
+    for (int64_t r = 0; r < im->H; r++) {
+        for (int64_t c = 0; c < im->W; c++) {
+            int32_t *e = &label[r * im->W + c];
+            const uint8_t v = im->img[r * im->stride + c];
+            *e = 0;
+            if (v == 0)
+                continue;
+            int32_t l = 0;
+            for (int k = 0; k < nn; k++) {
+                const int64_t rr = r + nb[k][0], cc = c + nb[k][1];
+                if (rr < 0 || cc < 0 || cc >= im->W || im->img[rr * im->stride + cc] != v)
+                    continue;
+                const int32_t ln = label[rr * im->W + cc];
+                l = l ? merge(p, l, ln) : p[ln];
+            }
+            if (!l) {
+                l = count;
+                p[count] = count;
+                count++;
+            }
+            *e = l;
+        }
+    }
+    return count - 1;
+}
+
 /* ====================================================================== */
 /* Exported entry points.  All return the number of components K >= 0, or  */
 /* -1 on an argument or allocation error.  labels is a dense H x W int32    */
@@ -385,6 +433,23 @@ int64_t oracle_cclremsp(const uint8_t *img, int64_t H, int64_t W, int64_t stride
     if (!p)
         return -1;
     int32_t count = scan_cclremsp(&im, conn, labels, p);
+    int32_t k = flatten(p, count);
+    labeling_phase(labels, &im, p);
+    free(p);
+    return k;
+}
+
+/* Gray-level labeling: scan_gray, flatten, labeling.  Any two 4-adjacent  */
+/* pixels may hold different values, so up to H*W labels are handed out.   */
+int64_t oracle_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels)
+{
+    if (bad_args(img, H, W, stride, conn, labels))
+        return -1;
+    image_t im = {img, H, W, stride};
+    int32_t *p = (int32_t *)malloc((size_t)(H * W + 2) * sizeof(int32_t));
+    if (!p)
+        return -1;
+    int32_t count = scan_gray(&im, conn, labels, p);
     int32_t k = flatten(p, count);
     labeling_phase(labels, &im, p);
     free(p);

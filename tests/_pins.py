@@ -92,3 +92,37 @@ def read_golden(path):
         if s:
             out[conn] = (np.array(s["rows"], dtype=np.int32), s["K"])
     return img, out
+
+
+def bfs_gray_labels(img, conn):
+    """Textbook flood fill for the gray-level extension: object pixels are
+    nonzero, neighbours connect when their values are equal; components
+    numbered by first pixel in raster order."""
+    img = np.asarray(img)
+    H, W = img.shape
+    out = np.zeros((H, W), dtype=np.int32)
+    offs = OFFS8 if conn == 8 else OFFS4
+    k = 0
+    for r in range(H):
+        for c in range(W):
+            v = img[r, c]
+            if v and out[r, c] == 0:
+                k += 1
+                out[r, c] = k
+                q = deque([(r, c)])
+                while q:
+                    y, x = q.popleft()
+                    for dy, dx in offs:
+                        yy, xx = y + dy, x + dx
+                        if 0 <= yy < H and 0 <= xx < W and img[yy, xx] == v and out[yy, xx] == 0:
+                            out[yy, xx] = k
+                            q.append((yy, xx))
+    return out
+
+
+def all_gray_images(H, W, levels):
+    """Every H x W image with pixel values in range(levels)."""
+    n = H * W
+    codes = np.arange(levels ** n, dtype=np.int64)
+    digits = (codes[:, None] // (levels ** np.arange(n))[None, :]) % levels
+    return digits.reshape(-1, H, W).astype(np.uint8)

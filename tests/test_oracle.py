@@ -391,3 +391,86 @@ def test_binarize_pins():
     assert lab4.tolist() == [[0, 1, 0], [2, 0, 3], [2, 0, 0]]
     assert oracle.label(img, 8, level=0).tolist() == oracle.label((img > 0).astype(np.uint8), 8).tolist()
     assert oracle.label(img, 8, level=255).max() == 0
+
+
+# ------------------------------------------------------------ gray levels
+@pytest.mark.parametrize("conn", [8, 4])
+def test_gray_exhaustive(conn):
+    """Gray-level oracle against flood fill on every 3x3 image over values
+    {0, 1, 2} and every 2x3 image over {0..3}."""
+    for shape, levels in (((3, 3), 3), ((2, 3), 4)):
+        imgs = _pins.all_gray_images(*shape, levels)
+        for j in range(imgs.shape[0]):
+            got, k = oracle.gray(imgs[j], conn)
+            ref = _pins.bfs_gray_labels(imgs[j], conn)
+            assert np.array_equal(got, ref), (shape, j)
+            assert k == ref.max()
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_gray_scipy_and_binary(conn):
+    """Per-value scipy labeling, renumbered by first raster pixel, equals the
+    gray oracle; on 0/1 images the gray oracle is the binary one."""
+    import scipy.ndimage as ndi
+    rng = np.random.default_rng(5)
+    st = np.ones((3, 3)) if conn == 8 else None
+    for trial in range(6):
+        H, W = rng.integers(20, 90, size=2)
+        img = rng.integers(0, 4, size=(H, W)).astype(np.uint8)
+        comb = np.zeros((H, W), np.int64)
+        base = 0
+        for v in range(1, 4):
+            lab, n = ndi.label(img == v, structure=st)
+            comb[lab > 0] = lab[lab > 0] + base
+            base += n
+        canon, kk = oracle.canonical(comb.astype(np.int32))
+        got, k = oracle.gray(img, conn)
+        assert np.array_equal(got, canon) and k == kk
+        b = (rng.random((H, W)) < 0.5).astype(np.uint8)
+        assert np.array_equal(oracle.gray(b, conn)[0], oracle.cclremsp(b, conn)[0])
+
+
+def test_gray_closed_form():
+    """Columns of distinct values: each column is one component under both
+    connectivities (diagonal neighbours differ), label = column + 1."""
+    H, W = 17, 200
+    img = np.tile((1 + np.arange(W) % 250).astype(np.uint8), (H, 1))
+    for conn in (8, 4):
+        got, k = oracle.gray(img, conn)
+        assert k == W and np.array_equal(got, np.tile(np.arange(1, W + 1, dtype=np.int32), (H, 1)))
+
+
+GRAY_MUTANTS = [
+    # values ignored: any two object neighbours connect
+    ("im->img[rr * im->stride + cc] != v)", "im->img[rr * im->stride + cc] == 0)"),
+    # only the first equal neighbour is used (no merge)
+    ("l = l ? merge(p, l, ln) : p[ln];", "l = l ? l : p[ln];"),
+]
+
+
+@pytest.mark.parametrize("i", range(len(GRAY_MUTANTS)))
+def test_gray_planted_mistakes_are_caught(tmp_path, i):
+    old, new = GRAY_MUTANTS[i]
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "ccl_oracle.c")).read()
+    assert src.count(old) == 1, old
+    mut = tmp_path / f"gmutant{i}.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / f"gmutant{i}.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(mut)], check=True)
+    lib = ctypes.CDLL(str(so))
+    u8p, i32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_gray.argtypes = [u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, i32p]
+    lib.oracle_gray.restype = ctypes.c_int64
+    imgs = _pins.all_gray_images(3, 3, 3)
+    out = np.empty((3, 3), np.int32)
+    caught = False
+    for conn in (8, 4):
+        for j in range(imgs.shape[0]):
+            img = np.ascontiguousarray(imgs[j])
+            lib.oracle_gray(img.ctypes.data_as(u8p), 3, 3, 3, conn, out.ctypes.data_as(i32p))
+            if not np.array_equal(out, _pins.bfs_gray_labels(img, conn)):
+                caught = True
+                break
+        if caught:
+            break
+    assert caught, f"gray mutant {i} survived"
