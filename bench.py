@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--p", type=float, default=0.5, help="Bernoulli foreground probability")
     ap.add_argument("--content", choices=["bernoulli", "grf", "gray"], default="bernoulli",
                     help="gray: grayscale bytes binarized inside the labeling at --level")
+    ap.add_argument("--gray-bins", type=int, default=0,
+                    help="gray-level labeling (equal-valued neighbours connect) of the grayscale field "
+                         "quantized into this many-wide value bins (0 = binary labeling)")
     ap.add_argument("--level", type=int, default=None,
                     help="foreground iff byte > level (default 0 = nonzero; 127 for --content gray)")
     ap.add_argument("--sigma", type=float, default=8.0, help="GRF smoothing (px) when --content grf")
@@ -232,24 +235,36 @@ def main():
     dev = torch.device("cuda:0")
     S = args.size
     stride = S if args.pitch <= 0 else (S + args.pitch - 1) // args.pitch * args.pitch
-    level = args.level if args.level is not None else (127 if args.content == "gray" else 0)
+    gray = args.gray_bins > 0
+    if gray and args.content != "gray":
+        ap.error("--gray-bins needs --content gray")
+    level = args.level if args.level is not None else (127 if args.content == "gray" and not gray else 0)
     if args.content == "grf":
         img = inputs.grf(S, S, args.sigma, args.q, seed=0, device=dev, stride=stride)
         content = f"thresholded Gaussian random field sigma={args.sigma} q={args.q} seed 0"
     elif args.content == "gray":
         img = inputs.gray(S, S, args.sigma, seed=0, device=dev, stride=stride)
         content = f"grayscale Gaussian field sigma={args.sigma} seed 0"
+        if args.gray_bins > 0:
+            img.copy_(img // args.gray_bins)
+            content += f", bytes // {args.gray_bins}, gray-level labeling"
     else:
         img = inputs.bernoulli(S, S, args.p, seed=0, device=dev, stride=stride)
         content = f"Bernoulli p={args.p} seed 0"
     out = torch.empty((S, S), dtype=torch.int32, device=dev)
     kdev = torch.zeros(1, dtype=torch.int32, device=dev)
     scan = ccl.SCAN_ROW if args.scan == "row" else ccl.SCAN_PAIR
-    ccl.reserve(ccl.workspace_bytes(S, S, args.conn, args.tile, scan))
-    th, tw = ccl.tile_shape(args.tile, args.conn, scan)
+    ccl.reserve(ccl.workspace_bytes(S, S, args.conn, args.tile, scan) * (2 if gray else 1))
+    th, tw = ccl.tile_shape(args.tile, args.conn, scan, gray)
+
+    def step(kout=None):
+        if gray:
+            ccl.label_gray(img, args.conn, out=out, tile=args.tile, num_components=kout, level=level)
+        else:
+            ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kout, level=level, scan=scan)
 
     for _ in range(args.warmup):
-        ccl.label(img, args.conn, out=out, tile=args.tile, level=level, scan=scan)
+        step()
     torch.cuda.synchronize()
 
     ccl.profile(True)
@@ -260,7 +275,7 @@ def main():
     t0 = time.perf_counter()
     start.record()
     for _ in range(args.steps):
-        ccl.label(img, args.conn, out=out, tile=args.tile, num_components=kdev, level=level, scan=scan)
+        step(kdev)
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -283,7 +298,7 @@ def main():
     alg_bytes = PHASE_BYTES_PER_PX[dom] * px
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     workload_key = {"bernoulli": f"bernoulli{args.p}", "grf": f"grf{args.sigma}_{args.q}",
-                    "gray": f"gray{args.sigma}_level{level}"}[args.content] + \
+                    "gray": f"gray{args.sigma}_level{level}" + (f"_bins{args.gray_bins}" if gray else "")}[args.content] + \
         f"_{S}x{S}_conn{args.conn}_tile{th}x{tw}" + (f"_pitch{stride}" if stride != S else "") + \
         ("_scanrow" if args.scan == "row" else "")
     traffic = load_traffic(dom, workload_key)
@@ -305,7 +320,7 @@ def main():
             "workload": f"{S}x{S} uint8 {content}, {args.conn}-connectivity, canonical int32 labels"
                         + (f", foreground iff byte > {level}" if level else ""),
             "H": S, "W": S, "stride": stride, "conn": args.conn, "tile": [th, tw], "parallelism": "single GPU",
-            "level": level, "scan": args.scan,
+            "level": level, "scan": args.scan, "gray_levels": gray,
         },
         "roofline": {
             "bound": "hbm",
@@ -329,12 +344,15 @@ def main():
 
         import oracle
         host = img.cpu().numpy()  # H x W view (row pitch dropped on copy)
-        if level:
+        if level and not gray:
             host = oracle.binarize(host, level)
+        if level and gray:
+            host = np.where(host > level, host, 0).astype(np.uint8)
+        label_fn = oracle.gray if gray else oracle.cclremsp
         times, ref = [], None
         for _ in range(max(args.cpu_runs, 1)):
             t = time.perf_counter()
-            ref, kref = oracle.cclremsp(host, args.conn)
+            ref, kref = label_fn(host, args.conn)
             times.append(time.perf_counter() - t)
         if args.cpu_runs > 0:
             med = statistics.median(times)
@@ -343,13 +361,14 @@ def main():
                 "unit": "Gpixel/s",
                 "cores": 1,
                 "kind": "oracle",
-                "sample": f"the full {S}x{S} image, single-threaded C CCLRemSP, median of {len(times)} runs "
+                "sample": f"the full {S}x{S} image, single-threaded C "
+                          f"{'gray-level two-pass labeling' if gray else 'CCLRemSP'}, median of {len(times)} runs "
                           f"({med:.2f} s each)",
             }
         if not args.no_verify:
             record["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), ref)) and int(kdev.item()) == kref
 
-    if args.ablation_steps > 0 and args.conn == 8:
+    if args.ablation_steps > 0 and args.conn == 8 and not gray:
         # the paper's scan comparison (Table II) inside a tile: one-row runs
         # vs two-row runs, same image, same everything else
         other = ccl.SCAN_ROW if scan == ccl.SCAN_PAIR else ccl.SCAN_PAIR

@@ -50,7 +50,8 @@ typedef enum {
     CCL_ERR_LEVEL = -11,    /* threshold level outside 0..255                   */
     CCL_ERR_SCAN = -12,     /* unknown scan strategy                            */
     CCL_ERR_BUDGET = -13,   /* request needs more workspace than a server slot  */
-    CCL_ERR_TICKET = -14    /* unknown server ticket                            */
+    CCL_ERR_TICKET = -14,   /* unknown server ticket                            */
+    CCL_ERR_GRAY = -15      /* gray flag other than 0 or 1                      */
 } ccl_status;
 
 /*
@@ -115,7 +116,20 @@ int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int c
 int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
                     int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
 
-/* One image of a batch; fields as in ccl_label_level. */
+/*
+ * ccl_label_gray -- gray-level labeling, the extension Section V mentions
+ * (the abstract: adjacent pixels sharing the same features get the same
+ * label): object pixels are the bytes greater than `level` (0 = nonzero), and
+ * two neighbouring object pixels (4- or 8-neighbours) are connected when
+ * their bytes are equal.  On a 0/1 image this is ccl_label.  Numbering as
+ * for ccl_label (components ranked by smallest raster index).  The tile-local
+ * nodes are single-row runs of equal bytes.  Arguments and errors as for
+ * ccl_label_level.
+ */
+int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
+                   int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
+
+/* One image of a batch; fields as in ccl_label_level and ccl_label_gray. */
 typedef struct {
     const uint8_t *img;      /* device */
     int64_t H, W, stride;
@@ -124,6 +138,7 @@ typedef struct {
     int32_t *num_components; /* device or NULL */
     int level;               /* foreground iff byte > level; 0 = nonzero */
     int scan;                /* ccl_scan; 0 = CCL_SCAN_PAIR */
+    int gray;                /* 1: gray-level labeling (see ccl_label_gray; scan is ignored) */
 } ccl_image_desc;
 
 /*
@@ -174,9 +189,11 @@ int ccl_release(void);
 
 /* Tile configuration `id` (1-based; 0 = default) -> block rows and tile
  * width in pixels.  A tile is `block rows` x 2 image rows under
- * 8-connectivity (the scan takes two rows at a time) and `block rows` x 1
- * under 4-connectivity.  Returns CCL_OK, or CCL_ERR_TILE when id is out of
- * range.  ccl_tile_count() gives the number of configurations. */
+ * 8-connectivity with the row-pair scan (two rows at a time), `block rows`
+ * x 1 with single rows (4-connectivity, CCL_SCAN_ROW), and `block rows` / 2
+ * x 1 for gray levels (where every pixel may be its own run).  Returns
+ * CCL_OK, or CCL_ERR_TILE when id is out of range.  ccl_tile_count() gives
+ * the number of configurations. */
 int ccl_tile_config(int id, int *block_rows, int *tile_w);
 int ccl_tile_count(void);
 

@@ -29,7 +29,7 @@ class ImageDesc(ctypes.Structure):
     """ccl_image_desc of include/ccl.h."""
     _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
                 ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p),
-                ("level", ctypes.c_int), ("scan", ctypes.c_int)]
+                ("level", ctypes.c_int), ("scan", ctypes.c_int), ("gray", ctypes.c_int)]
 
 
 _lib.ccl_label.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _stream]
@@ -39,6 +39,9 @@ _lib.ccl_label_ex.restype = ctypes.c_int
 _lib.ccl_label_level.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
                                  _stream]
 _lib.ccl_label_level.restype = ctypes.c_int
+_lib.ccl_label_gray.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                _stream]
+_lib.ccl_label_gray.restype = ctypes.c_int
 _lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int, _stream]
 _lib.ccl_label_batch.restype = ctypes.c_int
 _lib.ccl_workspace_bytes.argtypes = [_i64, _i64, ctypes.c_int, ctypes.c_int]
@@ -100,7 +103,7 @@ STATUS = {
     "CCL_ERR_NULL": -1, "CCL_ERR_SHAPE": -2, "CCL_ERR_STRIDE": -3, "CCL_ERR_CONN": -4,
     "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
     "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11, "CCL_ERR_SCAN": -12,
-    "CCL_ERR_BUDGET": -13, "CCL_ERR_TICKET": -14,
+    "CCL_ERR_BUDGET": -13, "CCL_ERR_TICKET": -14, "CCL_ERR_GRAY": -15,
 }
 SCAN_PAIR, SCAN_ROW = 0, 1   # ccl_scan: two-row (default) / one-row tile-local scan
 
@@ -185,12 +188,31 @@ def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, til
     return out
 
 
+def label_gray(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
+               num_components: torch.Tensor | None = None, stream=None, level: int = 0) -> torch.Tensor:
+    """Gray-level labeling: object pixels are bytes > `level`; neighbouring
+    object pixels connect when their bytes are equal."""
+    H, W, stride = _img_geometry(img)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of the image's shape")
+    nc = 0
+    if num_components is not None:
+        if num_components.dtype != torch.int32 or num_components.numel() < 1 or not num_components.is_cuda:
+            raise ValueError("num_components must be a device int32 tensor")
+        nc = num_components.data_ptr()
+    _check(_lib.ccl_label_gray(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc or None,
+                               int(tile), _stream_handle(stream)))
+    return out
+
+
 def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: int, stream=None) -> int:
     """Direct ccl_label call with raw device pointers; returns the status."""
     return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
 
 
-def _descs(imgs, conns, outs, counts, levels=None, scans=None):
+def _descs(imgs, conns, outs, counts, levels=None, scans=None, grays=None):
     n = len(imgs)
     arr = (ImageDesc * max(n, 1))()
     for i, img in enumerate(imgs):
@@ -202,32 +224,37 @@ def _descs(imgs, conns, outs, counts, levels=None, scans=None):
         arr[i].num_components = counts[i].data_ptr() if counts is not None else None
         arr[i].level = int(levels[i]) if levels is not None else 0
         arr[i].scan = int(scans[i]) if scans is not None else 0
+        arr[i].gray = int(bool(grays[i])) if grays is not None else 0
     return arr
 
 
 def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
-                stream=None, level=0, scan=SCAN_PAIR):
+                stream=None, level=0, scan=SCAN_PAIR, gray=False):
     """Label a list of images with one launch per phase for the whole batch.
 
-    conn, level, scan: int or per-image list.  num_components: optional
-    device int32 tensor with one slot per image."""
+    conn, level, scan, gray: one value or a per-image list.  num_components:
+    optional device int32 tensor with one slot per image."""
     n = len(imgs)
     conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
     levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
     scans = list(scan) if isinstance(scan, (list, tuple)) else [scan] * n
+    grays = list(gray) if isinstance(gray, (list, tuple)) else [gray] * n
     if outs is None:
         outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
     counts = None
     if num_components is not None:
         counts = [num_components[i:i + 1] for i in range(n)]
-    arr = _descs(imgs, conns, outs, counts, levels, scans)
+    arr = _descs(imgs, conns, outs, counts, levels, scans, grays)
     _check(_lib.ccl_label_batch(arr, n, int(tile), _stream_handle(stream)))
     return outs
 
 
-def tile_shape(tile: int, conn: int, scan: int = SCAN_PAIR):
-    """(tile height, tile width) in pixels of configuration `tile` for `conn`."""
+def tile_shape(tile: int, conn: int, scan: int = SCAN_PAIR, gray: bool = False):
+    """(tile height, tile width) in pixels of configuration `tile` for `conn`
+    (gray-level tiles have half the block rows, one image row each)."""
     nsr, tw = tile_configs()[max(tile, 1) - 1]
+    if gray:
+        return nsr // 2, tw
     return nsr * (2 if conn == 8 and scan == SCAN_PAIR else 1), tw
 
 

@@ -32,7 +32,11 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 // Image rows per block row: two under 8-connectivity with the pair-row scan
 // (the default), one otherwise.
 inline int bh_of(int conn, int scan) { return (conn == 8 && scan == CCL_SCAN_PAIR) ? 2 : 1; }
-inline int bh_of(const ccl_image_desc &d) { return bh_of(d.conn, d.scan); }
+inline int bh_of(const ccl_image_desc &d) { return d.gray ? 1 : bh_of(d.conn, d.scan); }
+
+// Launch groups of a batch: row-pair runs, single-row runs, gray levels.
+enum Group { kPair = 0, kRow = 1, kGray = 2, kGroups = 3 };
+inline int group_of(const ccl_image_desc &d) { return d.gray ? kGray : (bh_of(d) == 2 ? kPair : kRow); }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
@@ -42,9 +46,11 @@ struct Layout {
     size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
-Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c) {
+// bh: image rows per block row; gray-level tiles hold half the rows (one
+// per block row) so that every pixel can be a node.
+Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c, bool gray = false) {
     Layout L{};
-    L.th = c.nsr * bh;
+    L.th = gray ? c.nsr / 2 : c.nsr * bh;
     L.NTY = (int32_t)((H + L.th - 1) / L.th);
     L.NTX = (int32_t)((W + c.tw - 1) / c.tw);
     L.NT = L.NTY * L.NTX;
@@ -62,7 +68,7 @@ Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c) {
         off = align_up(off + bytes);
         return at;
     };
-    L.masks = take(NT * L.nm * sizeof(uint32_t));
+    L.masks = take(NT * L.nm * sizeof(uint32_t) * (gray ? 2 : 1));  // gray: foreground, then same-as-left
     L.rt = take(NT * L.rcap * sizeof(uint16_t));
     L.cb = take(NT * L.rw * sizeof(uint32_t));
     L.cf = take(NT * L.rcap * sizeof(int32_t));
@@ -98,6 +104,8 @@ int check_level(int level) { return (level < 0 || level > 255) ? CCL_ERR_LEVEL :
 int check_opts(const ccl_image_desc &d) {
     if (d.scan != CCL_SCAN_PAIR && d.scan != CCL_SCAN_ROW)
         return CCL_ERR_SCAN;
+    if (d.gray != 0 && d.gray != 1)
+        return CCL_ERR_GRAY;
     return check_level(d.level);
 }
 
@@ -275,12 +283,13 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
 
-int dispatch(const TileCfg &c, int bh, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
+int dispatch(const TileCfg &c, int group, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
              hipStream_t s) {
-#define CCL_TILE_CASE(N_, W_)                                                   \
-    if (c.nsr == N_ && c.tw == W_)                                              \
-        return bh == 2 ? launch_all<N_, W_, 2>(b, tiles, edges, blocks, nimg, s) \
-                       : launch_all<N_, W_, 1>(b, tiles, edges, blocks, nimg, s);
+#define CCL_TILE_CASE(N_, W_)                                                            \
+    if (c.nsr == N_ && c.tw == W_)                                                       \
+        return group == kPair ? launch_all<N_, W_, 2>(b, tiles, edges, blocks, nimg, s) \
+             : group == kRow  ? launch_all<N_, W_, 1>(b, tiles, edges, blocks, nimg, s) \
+                              : launch_all<N_, W_, 0>(b, tiles, edges, blocks, nimg, s);
     CCL_TILE_CASE(32, 256)
     CCL_TILE_CASE(16, 256)
     CCL_TILE_CASE(16, 512)
@@ -297,7 +306,7 @@ int dispatch(const TileCfg &c, int bh, const Batch &b, int64_t tiles, int64_t ed
 // is built in `htab` (pinned host memory that stays untouched until the
 // stream has passed the copy) or, when htab is NULL, in a temporary.
 int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
-              const std::vector<size_t> &offs, char *base, Img *dtab, int bh, const TileCfg &c,
+              const std::vector<size_t> &offs, char *base, Img *dtab, int group, const TileCfg &c,
               hipStream_t stream, bool table_ready = false, Img *htab = nullptr) {
     const int n = (int)idx.size();
     if (n == 0)
@@ -328,14 +337,14 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
             return CCL_ERR_HIP;
         b.tab = dtab;
     }
-    return dispatch(c, bh, b, tiles, edges, blocks, n, stream);
+    return dispatch(c, group, b, tiles, edges, blocks, n, stream);
 }
 
 size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
                    std::vector<size_t> *offs) {
     size_t off = align_up((size_t)n * sizeof(Img));
     for (int i = 0; i < n; i++) {
-        Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), c);
+        Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), c, descs[i].gray != 0);
         if (lays)
             lays->push_back(L);
         if (offs)
@@ -351,15 +360,19 @@ int run_batch_in(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream
     std::vector<Layout> lays;
     std::vector<size_t> offs;
     batch_bytes(descs, n, c, &lays, &offs);
-    std::vector<int> g2, g1;  // by image rows per block row
+    std::vector<int> g[kGroups];
     for (int i = 0; i < n; i++)
-        (bh_of(descs[i]) == 2 ? g2 : g1).push_back(i);
+        g[group_of(descs[i])].push_back(i);
     Img *dtab = reinterpret_cast<Img *>(base);
-    int st = run_group(descs, g2, lays, offs, base, dtab, 2, c, stream, false, htab);
-    if (st != CCL_OK)
-        return st;
-    return run_group(descs, g1, lays, offs, base, dtab + g2.size(), 1, c, stream, false,
-                     htab ? htab + g2.size() : nullptr);
+    size_t at = 0;
+    for (int k = 0; k < kGroups; k++) {
+        const int st = run_group(descs, g[k], lays, offs, base, dtab + at, k, c, stream, false,
+                                 htab ? htab + at : nullptr);
+        if (st != CCL_OK)
+            return st;
+        at += g[k].size();
+    }
+    return CCL_OK;
 }
 
 int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream) {
@@ -415,7 +428,21 @@ int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, in
     TileCfg c;
     if ((st = resolve_tile(tile, &c)) != CCL_OK)
         return st;
-    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR};
+    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR, 0};
+    return run_batch(&d, 1, c, stream);
+}
+
+int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
+                   int32_t *labels, int32_t *num_components, int tile, hipStream_t stream) {
+    int st = check_image(img, H, W, stride, conn, labels);
+    if (st != CCL_OK)
+        return st;
+    if ((st = check_level(level)) != CCL_OK)
+        return st;
+    TileCfg c;
+    if ((st = resolve_tile(tile, &c)) != CCL_OK)
+        return st;
+    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_ROW, 1};
     return run_batch(&d, 1, c, stream);
 }
 
@@ -456,7 +483,7 @@ size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile) {
     if (check_image(&dummy, H, W, W, conn, &dummy) != CCL_OK)
         return 0;
     ccl_image_desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy),
-                     nullptr, 0, CCL_SCAN_PAIR};
+                     nullptr, 0, CCL_SCAN_PAIR, 0};
     return batch_bytes(&d, 1, c, nullptr, nullptr);
 }
 
@@ -500,13 +527,13 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
         return CCL_ERR_NOMEM;
     }
     char *base = static_cast<char *>(g->ws);
-    std::vector<int> g8, g4;  // by image rows per block row (2, 1)
+    std::vector<int> grp[kGroups];
     for (int i = 0; i < n; i++)
-        (bh_of(descs[i]) == 2 ? g8 : g4).push_back(i);
+        grp[group_of(descs[i])].push_back(i);
     Img *dtab = reinterpret_cast<Img *>(base);
-    st = upload_group_table(descs, g8, lays, offs, base, dtab);
-    if (st == CCL_OK)
-        st = upload_group_table(descs, g4, lays, offs, base, dtab + g8.size());
+    size_t at[kGroups] = {0, grp[0].size(), grp[0].size() + grp[1].size()};
+    for (int k = 0; k < kGroups && st == CCL_OK; k++)
+        st = upload_group_table(descs, grp[k], lays, offs, base, dtab + at[k]);
     hipStream_t cs = nullptr;
     if (st == CCL_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
         st = CCL_ERR_HIP;
@@ -514,8 +541,9 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             st = CCL_ERR_HIP;
         } else {
-            int s1 = run_group(descs, g8, lays, offs, base, dtab, 2, c, cs, true);
-            int s2 = s1 == CCL_OK ? run_group(descs, g4, lays, offs, base, dtab + g8.size(), 1, c, cs, true) : s1;
+            int s2 = CCL_OK;
+            for (int k = 0; k < kGroups && s2 == CCL_OK; k++)
+                s2 = run_group(descs, grp[k], lays, offs, base, dtab + at[k], k, c, cs, true);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &graph);
             st = s2 != CCL_OK ? s2 : (e == hipSuccess ? CCL_OK : CCL_ERR_HIP);
@@ -650,6 +678,7 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_SCAN: return "unknown scan strategy";
     case CCL_ERR_BUDGET: return "request needs more workspace than a server slot holds";
     case CCL_ERR_TICKET: return "unknown server ticket";
+    case CCL_ERR_GRAY: return "gray must be 0 or 1";
     default: return "unknown status";
     }
 }
@@ -704,7 +733,7 @@ struct ccl_server {
     std::thread th;
 
     size_t bytes_of(const ccl_image_desc &d) const {
-        return ccl::layout_of(d.H, d.W, ccl::bh_of(d), tile).bytes;
+        return ccl::layout_of(d.H, d.W, ccl::bh_of(d), tile, d.gray != 0).bytes;
     }
 
     void finish(ccl::ServerSlot &sl, Clock::time_point now) {

@@ -98,14 +98,20 @@ __device__ __forceinline__ const Img &find_img(const Batch &b, int32_t item, int
 }
 
 // ------------------------------------------------------------------------
-// Tile geometry.  NSR block rows of BH image rows (BH = 2 for 8-conn, 1 for
-// 4-conn), TW columns, NW mask words per row.
+// Tile geometry.  NSR block rows of BH image rows (BH = 2: runs of row
+// pairs, 8-conn; BH = 1: runs of single rows), TW columns, NW mask words per
+// row.  BH = 0 is the gray-level form: single rows, NSR / 2 of them, so that
+// the node capacity (NSR * TW / 2) covers every pixel of the tile (runs of
+// equal bytes may touch each other).
 // ------------------------------------------------------------------------
 template <int NSR, int TW, int BH>
 struct Geo {
-    static constexpr int TH = NSR * BH;
+    static constexpr bool GRAY = BH == 0;
+    static constexpr int RB = GRAY ? 1 : BH;          // image rows per block row
+    static constexpr int NBR = GRAY ? NSR / 2 : NSR;  // block rows
+    static constexpr int TH = NBR * RB;
     static constexpr int NW = TW / 32;
-    static constexpr int NU = NSR * NW;                        // (block row, word) units
+    static constexpr int NU = NBR * NW;                        // (block row, word) units
     static constexpr int NM = TH * NW;                         // mask words
     static constexpr int RCAP = NSR * (TW / 2);                // most nodes a tile can hold
     static constexpr int RW = RCAP / 32;                       // words of a node/component bitmask
@@ -265,6 +271,59 @@ __device__ __forceinline__ uint32_t gt16(u32x4 v, uint32_t k) {
     return gt4<HI>(v.x, k) | (gt4<HI>(v.y, k) << 4) | (gt4<HI>(v.z, k) << 8) | (gt4<HI>(v.w, k) << 12);
 }
 
+// 4 bytes -> 4 bits: byte == 0 (the complement of the nonzero test above).
+__device__ __forceinline__ uint32_t z4(uint32_t x) {
+    const uint32_t t = ~((((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x)) & 0x80808080u;
+    return (t * 0x00204081u) >> 28;
+}
+
+// 32 equality bits of two 32-byte groups (8 dwords each).
+__device__ __forceinline__ uint32_t eq32(const uint32_t *a, const uint32_t *b) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+        m |= z4(a[j] ^ b[j]) << (4 * j);
+    return m;
+}
+
+// The 32 bytes of row y from column x (x % 32 == 0) as 8 dwords; bytes
+// outside the image read as 0.
+__device__ __forceinline__ void load_bytes(const Img &im, int y, int x, uint32_t *d) {
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+        d[j] = 0u;
+    if (y >= im.H || x >= im.W)
+        return;
+    const uint8_t *p = im.img + (int64_t)y * im.stride + x;
+    if (x + 32 <= im.W && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
+        const u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        const u32x4 b = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + 16));
+        d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
+        d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
+        return;
+    }
+    const int n = im.W - x < 32 ? im.W - x : 32;
+    for (int i = 0; i < n; i++)
+        d[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+}
+
+// Foreground bits (byte > level) of 32 bytes held as 8 dwords.
+__device__ __forceinline__ uint32_t fg32(const uint32_t *d, int lv) {
+    uint32_t m = 0;
+    if (lv < 128) {
+        const uint32_t k = (uint32_t)(127 - lv) * 0x01010101u;
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            m |= gt4<false>(d[j], k) << (4 * j);
+    } else {
+        const uint32_t k = (uint32_t)(255 - lv) * 0x01010101u;
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            m |= gt4<true>(d[j], k) << (4 * j);
+    }
+    return m;
+}
+
 // 32 pixels of row y starting at column x (x % 32 == 0), foreground iff the
 // byte exceeds the image's level; outside = 0.
 __device__ __forceinline__ uint32_t load_word(const Img &im, int y, int x) {
@@ -351,10 +410,10 @@ struct RunLds {
 
 template <int NSR, int TW, int BH>
 __device__ __forceinline__ uint32_t block_mask(const uint32_t *M, int R, int w) {
-    constexpr int NW = Geo<NSR, TW, BH>::NW;
-    uint32_t m = M[(R * BH) * NW + w];
-    if (BH == 2)
-        m |= M[(R * BH + 1) * NW + w];
+    constexpr int NW = Geo<NSR, TW, BH>::NW, RB = Geo<NSR, TW, BH>::RB;
+    uint32_t m = M[(R * RB) * NW + w];
+    if (RB == 2)
+        m |= M[(R * RB + 1) * NW + w];
     return m;
 }
 
@@ -368,9 +427,13 @@ __device__ __forceinline__ int32_t node_at(const RunLds<NSR, TW, BH> &t, int R, 
 }
 
 // Fills S and base from M; returns the number of nodes (same on all threads).
+// Gray-level images (one row per block row): a run starts at every object
+// pixel that does not continue its left neighbour's run (E: same value as
+// the left neighbour).
 template <int NSR, int TW, int BH, int NT>
-__device__ int32_t number_runs(RunLds<NSR, TW, BH> &t) {
+__device__ int32_t number_runs(RunLds<NSR, TW, BH> &t, const uint32_t *E = nullptr) {
     using G = Geo<NSR, TW, BH>;
+    constexpr bool GRAY = G::GRAY;
     constexpr int NW = G::NW;
     constexpr int UPT = (G::NU + NT - 1) / NT;
     int32_t carry = 0;
@@ -380,9 +443,14 @@ __device__ int32_t number_runs(RunLds<NSR, TW, BH> &t) {
         int32_t cnt = 0;
         if (u < G::NU) {
             const int R = u / NW, w = u % NW;
-            uint32_t bm = block_mask<NSR, TW, BH>(t.M, R, w);
-            uint32_t bl = w ? block_mask<NSR, TW, BH>(t.M, R, w - 1) : 0u;
-            uint32_t s = bm & ~((bm << 1) | (bl >> 31));
+            uint32_t s;
+            if (GRAY) {
+                s = t.M[u] & ~E[u];
+            } else {
+                uint32_t bm = block_mask<NSR, TW, BH>(t.M, R, w);
+                uint32_t bl = w ? block_mask<NSR, TW, BH>(t.M, R, w - 1) : 0u;
+                s = bm & ~((bm << 1) | (bl >> 31));
+            }
             t.S[u] = s;
             cnt = __popc(s);
         }
@@ -412,18 +480,26 @@ struct ScanLate {
 template <int NSR, int TW, int BH>
 struct ScanLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
+    static constexpr bool GRAY = G::GRAY;
     static constexpr int PRCAP = (int)(sizeof(ScanLate<NSR, TW, BH>) / 4);
+    static constexpr int GN = GRAY ? G::NM : 1;
     int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
     uint16_t SP[G::RCAP];   // start of each node: block row * TW + column
+    // gray levels, bit per pixel: same value as the left neighbour (GE), as
+    // the pixel above (GV), above-left (GD1), above-right (GD2)
+    uint32_t GE[GN], GV[GN], GD1[GN], GD2[GN];
     union {
         uint32_t PR[PRCAP];  // during the union step: touching node pairs (x | y << 16)
         ScanLate<NSR, TW, BH> late;
+        uint8_t BY[GRAY ? G::TH * TW : 1];  // gray levels: the tile's bytes, until the masks exist
     };
+    static_assert(!GRAY || sizeof(BY) <= sizeof(ScanLate<NSR, TW, BH>), "gray tile layout");
 };
 
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     using G = Geo<NSR, TW, BH>;
+    constexpr bool GRAY = G::GRAY;
     constexpr int NT = kTileThreads;
     constexpr int MPT = (G::NM + NT - 1) / NT;
     constexpr int UPT = (G::NU + NT - 1) / NT;
@@ -444,19 +520,78 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     // 1. foreground masks (kept in LDS; stored for the labeling pass at the
     // end, so that no barrier waits on those stores)
     uint32_t mreg[MPT];
+    uint32_t ereg[GRAY ? MPT : 1];
 #pragma unroll
     for (int k = 0; k < MPT; k++) {
         const int i = tid + k * NT;
         if (i < G::NM) {
             const int r = i / NW, w = i % NW;
-            mreg[k] = load_word(im, y0 + r, x0 + (w << 5));
+            if (GRAY) {
+                uint32_t d[8];
+                load_bytes(im, y0 + r, x0 + (w << 5), d);
+                mreg[k] = fg32(d, im.level);
+                uint32_t *by = reinterpret_cast<uint32_t *>(t.BY + r * TW + (w << 5));
+#pragma unroll
+                for (int j = 0; j < 8; j++)
+                    by[j] = d[j];
+            } else {
+                mreg[k] = load_word(im, y0 + r, x0 + (w << 5));
+            }
             t.M[i] = mreg[k];
         }
     }
     __syncthreads();
+    if (GRAY) {
+        // equality of each object pixel with its left, upper, upper-left and
+        // upper-right neighbours inside the tile (bytes shifted by one)
+#pragma unroll
+        for (int k = 0; k < MPT; k++) {
+            const int i = tid + k * NT;
+            if (i < G::NM) {
+                const int r = i / NW, w = i % NW;
+                const uint32_t *cur = reinterpret_cast<const uint32_t *>(t.BY + r * TW + (w << 5));
+                uint32_t c[8], sh[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++)
+                    c[j] = cur[j];
+                const uint32_t m = mreg[k];
+                const uint32_t lb = w ? (uint32_t)t.BY[r * TW + (w << 5) - 1] : 0u;
+#pragma unroll
+                for (int j = 0; j < 8; j++)
+                    sh[j] = (c[j] << 8) | (j ? c[j - 1] >> 24 : lb);
+                // bit 0 of the tile row has no left neighbour in the tile
+                const uint32_t e = m & eq32(c, sh) & (w ? 0xFFFFFFFFu : 0xFFFFFFFEu);
+                ereg[k] = e;
+                t.GE[i] = e;
+                uint32_t v = 0u, d1 = 0u, d2 = 0u;
+                if (r > 0) {
+                    const uint32_t *up = reinterpret_cast<const uint32_t *>(t.BY + (r - 1) * TW + (w << 5));
+                    uint32_t u[8];
+#pragma unroll
+                    for (int j = 0; j < 8; j++)
+                        u[j] = up[j];
+                    v = m & eq32(c, u);
+                    const uint32_t ul = w ? (uint32_t)t.BY[(r - 1) * TW + (w << 5) - 1] : 0u;
+                    const uint32_t ur = (w < NW - 1) ? (uint32_t)t.BY[(r - 1) * TW + (w << 5) + 32] : 0u;
+#pragma unroll
+                    for (int j = 0; j < 8; j++)
+                        sh[j] = (u[j] << 8) | (j ? u[j - 1] >> 24 : ul);
+                    d1 = m & eq32(c, sh) & (w ? 0xFFFFFFFFu : 0xFFFFFFFEu);
+#pragma unroll
+                    for (int j = 0; j < 8; j++)
+                        sh[j] = (u[j] >> 8) | ((j < 7 ? u[j + 1] : ur) << 24);
+                    d2 = m & eq32(c, sh) & ((w < NW - 1) ? 0xFFFFFFFFu : 0x7FFFFFFFu);
+                }
+                t.GV[i] = v;
+                t.GD1[i] = d1;
+                t.GD2[i] = d2;
+            }
+        }
+        __syncthreads();
+    }
 
     // 2. block runs, their ordinals and start positions
-    const int32_t n_runs = number_runs<NSR, TW, BH, NT>(t);
+    const int32_t n_runs = number_runs<NSR, TW, BH, NT>(t, t.GE);
 #pragma unroll
     for (int k = 0; k < UPT; k++) {
         const int u = tid + k * NT;
@@ -495,8 +630,26 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
         const int R = u / NW, w = u % NW;
         cm1[k] = 0;
         cm2[k] = 0u;
-        if (h < LPU && R > 0) {
-            const int rm = R * BH, ru = R * BH - 1;
+        if (GRAY && h < LPU && R > 0) {
+            // gray levels (one row per block row): U1 at the first column of
+            // each stretch where the pixel above has the same value and both
+            // rows continue their runs; the diagonal contacts unless the
+            // vertical contact at c already joins the same two runs
+            const uint32_t V = t.GV[u], Vl = w ? t.GV[u - 1] >> 31 : 0u;
+            const uint32_t Em = t.GE[u], Eu = t.GE[u - NW];
+            const uint32_t EuR = (w < NW - 1) ? t.GE[u - NW + 1] : 0u;
+            const uint32_t u1 = V & ~(((V << 1) | Vl) & Em & Eu);
+            uint32_t u2 = 0u, u3 = 0u;
+            if (conn8) {
+                u3 = t.GD1[u] & ~(V & Eu);
+                u2 = t.GD2[u] & ~(V & ((Eu >> 1) | (EuR << 31)));
+            }
+            constexpr int PART = 32 / LPU;
+            const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
+            cm1[k] = (uint64_t)(u1 & mine) | ((uint64_t)(u3 & mine) << 32);
+            cm2[k] = u2 & mine;
+        } else if (!GRAY && h < LPU && R > 0) {
+            const int rm = R * G::RB, ru = R * G::RB - 1;
             const uint32_t m = t.M[rm * NW + w];
             const uint32_t mL = w ? t.M[rm * NW + w - 1] : 0u;
             const uint32_t up = t.M[ru * NW + w];
@@ -663,10 +816,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
         if (!((t.late.RRB[k >> 5] >> (k & 31)) & 1u))
             continue;
         int32_t key;
-        if (BH == 1) {
+        if (G::RB == 1) {
             key = sp;
         } else {
-            const int r0 = R * BH;
+            const int r0 = R * G::RB;
             key = (r0 + 1) * TW + col;  // no top pixel: the run's start in the lower row
             int ww = col >> 5, from = col & 31;
             for (;;) {
@@ -693,10 +846,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             const int side = i / NW, w = i % NW;
             if ((side == 0 && !top) || (side == 1 && !bot))
                 continue;
-            const int r = side ? TH - 1 : 0, R = r / BH;
-            const uint32_t m = t.M[r * NW + w];
-            const uint32_t mL = w ? t.M[r * NW + w - 1] : 0u;
-            uint32_t starts = m & ~((m << 1) | (mL >> 31));
+            const int r = side ? TH - 1 : 0, R = r / G::RB;
+            uint32_t starts;
+            if (G::RB == 1) {
+                starts = t.S[r * NW + w];   // run starts of the row itself
+            } else {
+                const uint32_t m = t.M[r * NW + w];
+                const uint32_t mL = w ? t.M[r * NW + w - 1] : 0u;
+                starts = m & ~((m << 1) | (mL >> 31));
+            }
             while (starts) {
                 const int bb = __ffs(starts) - 1;
                 starts &= starts - 1u;
@@ -710,7 +868,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             const int c = side ? TW - 1 : 0;
             if (!((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u))
                 continue;
-            const int32_t comp = t.late.RT[node_at(t, r / BH, c)];
+            const int32_t comp = t.late.RT[node_at(t, r / G::RB, c)];
             atomicOr(&t.late.RFB[comp >> 5], 1u << (comp & 31));
         }
     }
@@ -761,7 +919,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             continue;
         uint16_t v = kNone;
         if ((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u)
-            v = (uint16_t)rank_of(t.late.RFB, t.late.RFP, t.late.RT[node_at(t, r / BH, c)]);
+            v = (uint16_t)rank_of(t.late.RFB, t.late.RFP, t.late.RT[node_at(t, r / G::RB, c)]);
         *dst = v;
     }
     for (int r = tid; r < TH; r += NT)
@@ -781,12 +939,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
         im.tcnt[ti * 4 + 1] = n_comp;
         im.tcnt[ti * 4 + 2] = n_bound;
     }
-    uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+    uint32_t *gmask = im.masks + (int64_t)ti * G::NM * (GRAY ? 2 : 1);
 #pragma unroll
     for (int k = 0; k < MPT; k++) {
         const int i = tid + k * NT;
-        if (i < G::NM)
+        if (i < G::NM) {
             gmask[i] = mreg[k];
+            if (GRAY)
+                gmask[G::NM + i] = ereg[k];
+        }
     }
 }
 
@@ -816,9 +977,18 @@ __device__ __forceinline__ bool fg_at(const uint16_t *line, int pos, int n) {
     return pos >= 0 && pos < n && line[pos] != kNone;
 }
 
+// Gray levels: the byte at position `pos` of an edge line (a tile row for a
+// horizontal edge, a tile column for a vertical one); 0 outside the image.
+__device__ __forceinline__ uint32_t line_byte(const Img &im, bool horiz, int fixed, int pos, int n) {
+    if (pos < 0 || pos >= n)
+        return 0u;
+    return horiz ? im.img[(int64_t)fixed * im.stride + pos] : im.img[(int64_t)pos * im.stride + fixed];
+}
+
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     using G = Geo<NSR, TW, BH>;
+    constexpr bool GRAY = G::GRAY;
     constexpr int TH = G::TH;
     const int32_t item = blockIdx.x * kThreads + threadIdx.x;
     const Img &im = find_img(b, item, kEdge);
@@ -870,6 +1040,29 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     }
     uint64_t cm1 = (uint64_t)u1 | ((uint64_t)u3 << 32);  // partner at c (U1) or c-1 (U3)
     uint32_t cm2 = u2;                                    // partner at c+1 (U2)
+    if (GRAY) {
+        // gray levels: object pixels face each other across the edge and
+        // connect when their bytes are equal; every such position is a
+        // contact (repeats of one component pair are skipped below)
+        const int lo_fixed = horiz ? later_t * TH : later_t * TW;
+        uint32_t v = 0u, d1 = 0u, d2 = 0u;
+        uint32_t hp = line_byte(im, horiz, lo_fixed - 1, from - 1, n);
+        uint32_t hc = line_byte(im, horiz, lo_fixed - 1, from, n);
+        for (int c = 0; c < 32; c++) {
+            const uint32_t hn = line_byte(im, horiz, lo_fixed - 1, from + c + 1, n);
+            if ((m >> c) & 1u) {
+                const uint32_t lv = line_byte(im, horiz, lo_fixed, from + c, n);
+                v |= (uint32_t)(lv == hc) << c;
+                d1 |= (uint32_t)(lv == hp) << c;
+                d2 |= (uint32_t)(lv == hn) << c;
+            }
+            hp = hc;
+            hc = hn;
+        }
+        // (an equal byte is an object pixel too, since the levels match)
+        cm1 = (uint64_t)v | (conn8 ? ((uint64_t)(d1 & (from > 0 ? 0xFFFFFFFFu : 0xFFFFFFFEu)) << 32) : 0ull);
+        cm2 = conn8 ? d2 : 0u;
+    }
     constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
     uint64_t *P = im.uf;
     // flat loop: one union step per iteration, next contact when one ends;
@@ -1109,14 +1302,17 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
 template <int NSR, int TW, int BH>
 struct RelabelLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
+    static constexpr bool GRAY = G::GRAY;
     uint16_t RT[G::RCAP];   // local component of each node
     int32_t CF[G::RCAP];    // final label of each local component
     int32_t RF[G::RCAP];    // final label of each node
+    uint32_t E[GRAY ? G::NM : 1];  // gray levels: same value as the left neighbour
 };
 
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
+    constexpr bool GRAY = G::GRAY;
     constexpr int NW = G::NW, TH = G::TH;
     constexpr int NT = kTileThreads;
     constexpr int MPT = (G::NM + NT - 1) / NT;
@@ -1130,6 +1326,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     // of the tile after it (which size those table loads) too, so no load
     // waits on another.
     uint32_t pm[MPT];
+    uint32_t pe[GRAY ? MPT : 1];
     uint32_t prt[TPT];
     int32_t pcf[TPT];
     int pn_runs = 0, pn_comp = 0;   // counts of the tile whose tables are in registers
@@ -1147,11 +1344,13 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         const int ti = tile - im.tile0;
         pn_runs = qn_runs;
         pn_comp = qn_comp;
-        const uint32_t *gmask = im.masks + (int64_t)ti * G::NM;
+        const uint32_t *gmask = im.masks + (int64_t)ti * G::NM * (GRAY ? 2 : 1);
 #pragma unroll
         for (int k = 0; k < MPT; k++) {
             const int i = tid + k * NT;
             pm[k] = i < G::NM ? gmask[i] : 0u;
+            if (GRAY)
+                pe[k] = i < G::NM ? gmask[G::NM + i] : 0u;
         }
         const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
         const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
@@ -1176,8 +1375,11 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
 #pragma unroll
         for (int k = 0; k < MPT; k++) {
             const int i = tid + k * NT;
-            if (i < G::NM)
+            if (i < G::NM) {
                 t.M[i] = pm[k];
+                if (GRAY)
+                    t.E[i] = pe[k];
+            }
         }
 #pragma unroll
         for (int k = 0; k < TPT; k++) {
@@ -1188,7 +1390,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
                 t.CF[i] = pcf[k];
         }
         __syncthreads();
-        number_runs<NSR, TW, BH, NT>(t);
+        number_runs<NSR, TW, BH, NT>(t, t.E);
         for (int k = tid; k < pn_runs; k += NT)
             t.RF[k] = t.CF[t.RT[k]];
         __syncthreads();
@@ -1203,7 +1405,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
             const int y = y0 + r;
             if (y >= im.H)
                 break;
-            const int R = r / BH;
+            const int R = r / G::RB;
             for (int q = lane; q < TW / 4; q += 64) {
                 const int c0 = q * 4, x = x0 + c0;
                 if (x >= im.W)

@@ -25,8 +25,9 @@ largest is 465.20 MB, Table III).  Those images are not available here:
   aspect log-uniform in [0.25, 4], W = clamp(round(H*aspect), 64, 4096);
   content Bernoulli p ~ U[0.2, 0.8] or GRF sigma ~ U[1, 16] at q = 0.5.
 * ``gray``       -- a grayscale image (bytes 0..255) for the fused
-  threshold: a Gaussian random field as in ``grf``, standardized and mapped
-  to 128 + 40 * z, rounded and clipped.
+  threshold and, quantized to a few levels (``gray(...) // k``), for
+  gray-level labeling: a Gaussian random field as in ``grf``, standardized
+  and mapped to 128 + 40 * z, rounded and clipped.
 * ``serve_specs`` -- a request stream for the server: Poisson arrival times
   at a given rate, 95% of sizes as in ``batch_specs`` and 5% with sides
   log-uniform up to 8192, connectivity 4 or 8 with equal probability.
@@ -153,7 +154,7 @@ def gray(H: int, W: int, sigma: float = 4.0, seed: int = 0, device="cpu", stride
     fx = torch.fft.rfftfreq(W, device=device, dtype=torch.float32)
     gain = torch.exp(-2.0 * (math.pi * sigma) ** 2 * (fy[:, None] ** 2 + fx[None, :] ** 2))
     field = torch.fft.irfft2(torch.fft.rfft2(noise) * gain, s=(H, W))
-    z = (field - field.mean()) / field.std().clamp_min(1e-12)
+    z = (field - field.mean()) / field.std(correction=0).clamp_min(1e-12)
     out = _alloc(H, W, stride, dst)
     out.copy_(torch.clamp(torch.round(128.0 + 40.0 * z), 0, 255).to(torch.uint8))
     return out

@@ -71,6 +71,11 @@ def test_status_codes_on_host():
     arr[1].scan = 2
     assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_SCAN"]
     arr[1].scan = 0
+    arr[1].gray = 3
+    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_GRAY"]
+    arr[1].gray = 0
+    assert lib.ccl_label_gray(dummy, 10, 10, 10, 300, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
+    assert lib.ccl_label_gray(dummy, 10, 10, 10, 0, 5, dummy, None, 0, None) == S["CCL_ERR_CONN"]
     arr[1].conn = 5
     # graph creation validates the same way before allocating anything
     h = ctypes.c_void_p()

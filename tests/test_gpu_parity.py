@@ -255,3 +255,68 @@ def test_one_row_scan_batch_and_full_size(ccl):
     got = ccl.label(img, 8, scan=ccl.SCAN_ROW)
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), oracle.label(img.cpu().numpy(), 8))
+
+
+# --------------------------------------------------------------- gray levels
+def _gray_check(ccl, img, conn, tile=0, level=0, what=""):
+    say(f"case gray {what} shape={tuple(img.shape)} conn={conn} tile={tile} level={level}")
+    k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    got = ccl.label_gray(img, conn, tile=tile, num_components=k, level=level)
+    torch.cuda.synchronize()
+    host = img.cpu().numpy()
+    if level:
+        host = np.where(host > level, host, 0).astype(np.uint8)
+    ref, kref = oracle.gray(host, conn)
+    g = got.cpu().numpy()
+    if not np.array_equal(g, ref):
+        bad = np.argwhere(g != ref)
+        r, c = bad[0]
+        raise AssertionError(f"gray {what}: {len(bad)} pixels differ; first at {(r, c)} gpu={g[r, c]} "
+                             f"oracle={ref[r, c]}")
+    assert int(k.item()) == kref
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_gray_levels_small_and_ragged(ccl, conn):
+    """Gray-level labeling against the oracle: few-valued noise (short runs,
+    many diagonal contacts), quantized smooth fields (large equal regions
+    meeting along long borders), odd and strided shapes, every tile."""
+    gen = torch.Generator().manual_seed(3)
+    for (H, W) in [(1, 1), (1, 300), (300, 1), (31, 255), (65, 513), (257, 1031)]:
+        noise = torch.randint(0, 4, (H, W), generator=gen, dtype=torch.int32).to(torch.uint8).to(DEV)
+        _gray_check(ccl, noise, conn, what="values 0..3")
+        field = (inputs.gray(H, W, 3.0, seed=H + W, device=DEV) // 48).contiguous()
+        _gray_check(ccl, field, conn, what="quantized field")
+    big = (inputs.gray(700, 900, 4.0, seed=8, device=DEV) // 40).contiguous()
+    for tile in range(0, len(ccl.tile_configs()) + 1):
+        _gray_check(ccl, big, conn, tile=tile, what="tile sweep")
+    base = (inputs.gray(300, 1100, 2.0, seed=10, device=DEV) // 30).contiguous()
+    _gray_check(ccl, base[:, 5:1030], conn, what="strided unaligned")
+    _gray_check(ccl, big, conn, level=3, what="level 3")
+
+
+def test_gray_binary_images_match_binary_labeling(ccl):
+    for name in ("spiral", "checkerboard", "comb", "diagonal", "ones", "zeros"):
+        img = inputs.adversarial(name, 600, 700, device=DEV)
+        for conn in (8, 4):
+            say(f"case gray==binary {name} conn={conn}")
+            a = ccl.label_gray(img, conn)
+            b = ccl.label(img, conn)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b)
+
+
+def test_gray_batch_and_full_size(ccl):
+    imgs = [(inputs.gray(200 + 37 * i, 300 + 11 * i, 2.0 + i, seed=i, device=DEV) // 32).contiguous()
+            for i in range(6)]
+    grays = [True, False, True, True, False, True]
+    conns = [8, 8, 4, 8, 4, 4]
+    say("case gray batch")
+    outs = ccl.label_batch(imgs, conns, gray=grays)
+    torch.cuda.synchronize()
+    for im, o, g, c in zip(imgs, outs, grays, conns):
+        host = im.cpu().numpy()
+        ref = oracle.gray(host, c)[0] if g else oracle.label(host, c)
+        assert np.array_equal(o.cpu().numpy(), ref)
+    img = (inputs.gray(16384, 16384, 6.0, seed=5, device=DEV) // 32).contiguous()
+    _gray_check(ccl, img, 8, what="16384^2 quantized field")
