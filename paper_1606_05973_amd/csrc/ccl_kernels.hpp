@@ -1303,7 +1303,6 @@ template <int NSR, int TW, int BH>
 struct RelabelLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
     static constexpr bool GRAY = G::GRAY;
-    uint16_t RT[G::RCAP];   // local component of each node
     int32_t CF[G::RCAP];    // final label of each local component
     int32_t RF[G::RCAP];    // final label of each node
     uint32_t E[GRAY ? G::NM : 1];  // gray levels: same value as the left neighbour
@@ -1316,7 +1315,10 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     constexpr int NW = G::NW, TH = G::TH;
     constexpr int NT = kTileThreads;
     constexpr int MPT = (G::NM + NT - 1) / NT;
-    constexpr int TPT = (G::RCAP + NT - 1) / NT;  // table entries per thread
+    // table entries prefetched per thread: node pairs (two u16 entries per
+    // load) and components; a tile with more nodes or components loads the
+    // rest when it is labeled (rare: dense noise has ~1/10 of the capacity)
+    constexpr int PJ = G::RB == 2 ? 2 : 3, CJ = G::RB == 2 ? 1 : 2;
     __shared__ RelabelLds<NSR, TW, BH> t;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -1324,11 +1326,12 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     // While a tile's stores drain, the next tile's mask and tables are
     // already in flight into registers, and the node and component counts
     // of the tile after it (which size those table loads) too, so no load
-    // waits on another.
+    // waits on another.  Few registers are held for this, so that four
+    // workgroups fit a CU.
     uint32_t pm[MPT];
     uint32_t pe[GRAY ? MPT : 1];
-    uint32_t prt[TPT];
-    int32_t pcf[TPT];
+    uint32_t prt[PJ];   // node pairs 2q, 2q+1 (q = tid + j * NT): components, packed
+    int32_t pcf[CJ];
     int pn_runs = 0, pn_comp = 0;   // counts of the tile whose tables are in registers
     int qn_runs = 0, qn_comp = 0;   // counts of the tile after it
     auto counts = [&](int tile) {
@@ -1352,13 +1355,17 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
             if (GRAY)
                 pe[k] = i < G::NM ? gmask[G::NM + i] : 0u;
         }
-        const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
+        const uint32_t *grt2 = reinterpret_cast<const uint32_t *>(im.rt + (int64_t)ti * G::RCAP);
         const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
 #pragma unroll
-        for (int k = 0; k < TPT; k++) {
-            const int i = tid + k * NT;
-            prt[k] = i < pn_runs ? grt[i] : 0u;
-            pcf[k] = i < pn_comp ? gcf[i] : 0;
+        for (int j = 0; j < PJ; j++) {
+            const int q = tid + j * NT;
+            prt[j] = 2 * q < pn_runs ? grt2[q] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < CJ; j++) {
+            const int c = tid + j * NT;
+            pcf[j] = c < pn_comp ? gcf[c] : 0;
         }
     };
     int tile = blockIdx.x;
@@ -1382,17 +1389,31 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
             }
         }
 #pragma unroll
-        for (int k = 0; k < TPT; k++) {
-            const int i = tid + k * NT;
-            if (i < pn_runs)
-                t.RT[i] = (uint16_t)prt[k];
-            if (i < pn_comp)
-                t.CF[i] = pcf[k];
+        for (int j = 0; j < CJ; j++) {
+            const int c = tid + j * NT;
+            if (c < pn_comp)
+                t.CF[c] = pcf[j];
+        }
+        if (pn_comp > CJ * NT) {
+            const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+            for (int c = CJ * NT + tid; c < pn_comp; c += NT)
+                t.CF[c] = gcf[c];
         }
         __syncthreads();
         number_runs<NSR, TW, BH, NT>(t, t.E);
-        for (int k = tid; k < pn_runs; k += NT)
-            t.RF[k] = t.CF[t.RT[k]];
+#pragma unroll
+        for (int j = 0; j < PJ; j++) {
+            const int q = tid + j * NT;
+            if (2 * q < pn_runs)
+                t.RF[2 * q] = t.CF[prt[j] & 0xFFFFu];
+            if (2 * q + 1 < pn_runs)
+                t.RF[2 * q + 1] = t.CF[prt[j] >> 16];
+        }
+        if (pn_runs > 2 * PJ * NT) {
+            const uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
+            for (int k = 2 * PJ * NT + tid; k < pn_runs; k += NT)
+                t.RF[k] = t.CF[grt[k]];
+        }
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) {
             fetch(tile + gridDim.x);
