@@ -97,6 +97,17 @@ __device__ __forceinline__ const Img &find_img(const Batch &b, int32_t item, int
     return b.tab[lo];
 }
 
+// Workgroups are dealt to the eight XCDs round robin (workgroup b runs on
+// XCD b % 8, each XCD with its own L2).  This gives each XCD a contiguous
+// range of the n tiles in raster order, so horizontally adjacent tiles, which
+// share the cache lines straddling their common edge, are read through the
+// same L2 at about the same time.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int q = n / kXcds, r = n % kXcds, x = b % kXcds, j = b / kXcds;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // ------------------------------------------------------------------------
 // Tile geometry.  NSR block rows of BH image rows (BH = 2: runs of row
 // pairs, 8-conn; BH = 1: runs of single rows), TW columns, NW mask words per
@@ -510,8 +521,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
     constexpr int NW = G::NW, TH = G::TH;
     constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
     __shared__ ScanLds<NSR, TW, BH> t;
-    const Img &im = find_img(b, blockIdx.x, kTile);
-    const int ti = blockIdx.x - im.tile0;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const Img &im = find_img(b, tile, kTile);
+    const int ti = tile - im.tile0;
     const int ty = ti / im.NTX, tx = ti % im.NTX;
     const int y0 = ty * TH, x0 = tx * TW;
     const int tid = threadIdx.x;
