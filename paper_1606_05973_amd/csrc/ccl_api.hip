@@ -42,7 +42,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
-    int32_t th, NTY, NTX, NT, nblk, nedge, nm, rcap, rw, cap;
+    int32_t th, NTY, NTX, NT, nblk, nedge, nm, rcap, rw, cap, hep, vep;
     size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
@@ -73,8 +73,10 @@ Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c, bool gray = fal
     L.cb = take(NT * L.rw * sizeof(uint32_t));
     L.cf = take(NT * L.rcap * sizeof(int32_t));
     L.tcnt = take(NT * 4 * sizeof(int32_t));
-    L.he = take((size_t)L.NTY * 2 * W * sizeof(uint16_t));
-    L.ve = take((size_t)L.NTX * 2 * H * sizeof(uint16_t));
+    L.hep = (int32_t)((W + 31) / 32 * 32);
+    L.vep = (int32_t)((H + 31) / 32 * 32);
+    L.he = take((size_t)L.NTY * 2 * L.hep * sizeof(uint16_t));
+    L.ve = take((size_t)L.NTX * 2 * L.vep * sizeof(uint16_t));
     L.uf = take(NT * L.cap * sizeof(uint64_t));
     L.bval = take(NT * L.cap * sizeof(int32_t));
     L.bkey = take(NT * L.cap * sizeof(uint16_t));
@@ -184,6 +186,8 @@ Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     im.NTX = L.NTX;
     im.conn = d.conn;
     im.level = d.level;
+    im.hep = L.hep;
+    im.vep = L.vep;
     im.nblk = L.nblk;
     return im;
 }

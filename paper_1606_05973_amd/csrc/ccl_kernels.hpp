@@ -53,8 +53,8 @@ struct Img {
     int32_t *cf;          // [NT][RCAP]  canonical key (local pixel index) of each local component,
                           //             replaced by its final label by the component-label kernel
     int32_t *tcnt;        // [NT][4]     nodes, components, boundary components
-    uint16_t *he;         // [NTY][2][W] boundary index of each top(0)/bottom(1) tile-row pixel
-    uint16_t *ve;         // [NTX][2][H] same for the left(0)/right(1) tile columns
+    uint16_t *he;         // [NTY][2][hep] boundary index of each top(0)/bottom(1) tile-row pixel
+    uint16_t *ve;         // [NTX][2][vep] same for the left(0)/right(1) tile columns
     uint64_t *uf;         // [NT][CAP]   global union-find: (key of parent << 32) | parent id
     int32_t *bval;        // [NT][CAP]   interior roots before it in its row -> offset -> final label
     uint16_t *bkey;       // [NT][CAP]   canonical key of boundary component j
@@ -64,6 +64,7 @@ struct Img {
     int64_t stride;
     int32_t H, W, NTY, NTX, conn;
     int32_t level;        // foreground iff byte > level (0..255; 0 = nonzero)
+    int32_t hep, vep;     // edge line pitches: W and H rounded up to 32 entries (64-byte lines)
     int32_t tile0;        // first tile of this image in a batch-wide tile numbering
     int32_t edge0;        // first edge segment (boundary merge kernel)
     int32_t scan0;        // first scan block
@@ -919,13 +920,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
             c = i % TW;
             r = side ? TH - 1 : 0;
             on = (side ? bot : top) && x0 + c < im.W;
-            dst = im.he + ((int64_t)ty * 2 + side) * im.W + x0 + c;
+            dst = im.he + ((int64_t)ty * 2 + side) * im.hep + x0 + c;
         } else {
             const int q = i - 2 * TW, side = q / TH;
             r = q % TH;
             c = side ? TW - 1 : 0;
             on = (side ? right : left) && y0 + r < im.H;
-            dst = im.ve + ((int64_t)tx * 2 + side) * im.H + y0 + r;
+            dst = im.ve + ((int64_t)tx * 2 + side) * im.vep + y0 + r;
         }
         if (!on)
             continue;
@@ -977,12 +978,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
 //      ends (diagonal).
 // At a cut U1 and U3 can both hold, so they are walked separately.
 // ------------------------------------------------------------------------
+// Foreground bits of positions from..from+31 of an edge line (from % 32 == 0,
+// lines 64-byte aligned): four 16-byte loads; positions at or past n are 0.
 __device__ __forceinline__ uint32_t line_mask(const uint16_t *line, int from, int n) {
+    const u32x4 *q = reinterpret_cast<const u32x4 *>(line + from);
     uint32_t m = 0;
-    for (int i = 0; i < 32; i++)
-        if (from + i < n && line[from + i] != kNone)
-            m |= 1u << i;
-    return m;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const u32x4 v = q[k];
+        const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int bit = k * 8 + j * 2;
+            m |= (uint32_t)((d[j] & 0xFFFFu) != kNone) << bit;
+            m |= (uint32_t)((d[j] >> 16) != kNone) << (bit + 1);
+        }
+    }
+    const int left = n - from;
+    return left >= 32 ? m : (left <= 0 ? 0u : m & ((1u << left) - 1u));
 }
 
 __device__ __forceinline__ bool fg_at(const uint16_t *line, int pos, int n) {
@@ -1018,16 +1031,16 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
         from = (e % nxs) << 5;
         n = im.W;
         period = TW;
-        lo = im.he + ((int64_t)later_t * 2 + 0) * im.W;
-        hi = im.he + ((int64_t)(later_t - 1) * 2 + 1) * im.W;
+        lo = im.he + ((int64_t)later_t * 2 + 0) * im.hep;
+        hi = im.he + ((int64_t)(later_t - 1) * 2 + 1) * im.hep;
     } else {
         e -= nH;
         later_t = 1 + e / nys;       // tile column of the right tiles
         from = (e % nys) << 5;
         n = im.H;
         period = TH;
-        lo = im.ve + ((int64_t)later_t * 2 + 0) * im.H;
-        hi = im.ve + ((int64_t)(later_t - 1) * 2 + 1) * im.H;
+        lo = im.ve + ((int64_t)later_t * 2 + 0) * im.vep;
+        hi = im.ve + ((int64_t)(later_t - 1) * 2 + 1) * im.vep;
     }
     const int earlier_t = later_t - 1;
     // cut[c]: a perpendicular tile edge lies between positions c-1 and c
