@@ -26,7 +26,7 @@ namespace {
 struct TileCfg {
     int nsr, tw;
 };
-constexpr TileCfg kTiles[] = {{32, 256}, {16, 256}, {16, 512}, {64, 128}, {32, 128}, {8, 512}};
+constexpr TileCfg kTiles[] = {{32, 256}, {16, 256}, {16, 512}, {64, 128}, {32, 128}, {8, 512}, {64, 256}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // Image rows per block row: two under 8-connectivity with the pair-row scan
@@ -300,6 +300,7 @@ int dispatch(const TileCfg &c, int group, const Batch &b, int64_t tiles, int64_t
     CCL_TILE_CASE(64, 128)
     CCL_TILE_CASE(32, 128)
     CCL_TILE_CASE(8, 512)
+    CCL_TILE_CASE(64, 256)
 #undef CCL_TILE_CASE
     return CCL_ERR_TILE;
 }

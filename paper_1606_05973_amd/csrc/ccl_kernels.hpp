@@ -315,8 +315,12 @@ __device__ __forceinline__ void load_bytes(const Img &im, int y, int x, uint32_t
         return;
     }
     const int n = im.W - x < 32 ? im.W - x : 32;
-    for (int i = 0; i < n; i++)
-        d[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (4 * j + q < n)
+                d[j] |= (uint32_t)p[4 * j + q] << (8 * q);
 }
 
 // Foreground bits (byte > level) of 32 bytes held as 8 dwords.
