@@ -1177,11 +1177,14 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
     const int64_t cbase = (int64_t)ti * G::CAP;
     // flat loop: every lane walks its components' parent chains one load per
     // iteration, without waiting for other lanes' longer chains; the walk's
-    // end (the root entry) is written back to the component's own entry
+    // end (the root entry) is written back to the component's own entry.
+    // All unions are done (previous kernel), so plain cached loads suffice:
+    // an entry read before another workgroup's write-back still points up
+    // the same tree, and roots never change here.
     int j = tid;
     uint32_t r = (uint32_t)(cbase + j);
     while (j < n) {
-        const uint64_t v = aload<__HIP_MEMORY_SCOPE_AGENT>(im.uf + r);
+        const uint64_t v = im.uf[r];
         if ((uint32_t)v != r) {
             r = (uint32_t)v;
             continue;
@@ -1189,7 +1192,7 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
         const uint32_t id = (uint32_t)(cbase + j);
         const bool is = r == id;
         if (!is)
-            astore<__HIP_MEMORY_SCOPE_AGENT>(im.uf + id, v);
+            im.uf[id] = v;
         im.broot[id] = is;
         if (is) {
             const int key = im.bkey[id];
