@@ -2,15 +2,19 @@
 """Throughput benchmark of the gfx950 two-pass connected component labeling.
 
 One step = one full ccl_label call (tile scan, boundary merge, flatten,
-rank scan, publish, labeling pass) on a device-resident image.  Default
-workload: the paper-scale single image, 21568 x 21568 uint8 (465.18 Mpx, the
-size of the paper's largest NLCD image at one byte per pixel), i.i.d.
-Bernoulli foreground p = 0.5 from seed 0, 8-connectivity.
+rank scan, component labels, labeling pass) on a device-resident image.
+Default workload: the paper-scale single image, 21568 x 21568 uint8
+(465.18 Mpx, the size of the paper's largest NLCD image at one byte per
+pixel), i.i.d. Bernoulli foreground p = 0.5 from seed 0, 8-connectivity.
 
 Prints ONE JSON line with the throughput (Gpixel/s), the roofline of the
 dominant kernel (its duration from HIP events recorded on the stream it runs
-on, during the timed steps), the CPU oracle timed on the host, and whether the
-benchmarked output is bit-exact against that oracle.
+on, during the timed steps), the CPU oracle timed on the host, whether the
+benchmarked output is bit-exact against that oracle, the two-row vs one-row
+scan comparison, the batched forms (256 uneven images: one batch call, the
+captured graph, a loop of single calls) and the served form (Poisson request
+streams through the continuous-batching server: p50/p99 latency, Gpixel/s,
+alone == mix).
 """
 from __future__ import annotations
 

@@ -163,54 +163,10 @@ __device__ __forceinline__ T acas(T *p, T expect, T v) {
 // many of them, every root stays its set's smallest node, and the loop ends.
 // The splice done by CAS rather than a plain store only skips a splice that
 // a concurrent change made stale.
-template <int S>
-__device__ void rem_union(int32_t *P, int32_t x, int32_t y) {
-    int32_t rx = x, ry = y;
-    int32_t px = aload<S>(P + rx);
-    int32_t py = aload<S>(P + ry);
-    while (px != py) {
-        const bool xs = px > py;
-        const int32_t n = xs ? rx : ry;
-        const int32_t pn = xs ? px : py;
-        const int32_t q = xs ? py : px;
-        const int32_t seen = acas<S>(P + n, pn, q);
-        const bool ok = seen == pn;
-        if (ok && pn == n)
-            return;
-        const int32_t nn = ok ? pn : n;
-        const int32_t np = aload<S>(P + nn);
-        rx = xs ? nn : rx;
-        px = xs ? np : px;
-        ry = xs ? ry : nn;
-        py = xs ? py : np;
-    }
-}
-
-// The same on the global array of packed entries (key of parent << 32 |
-// parent id): comparing packed parents compares their keys, so the root of
-// every set is the node with the smallest key.
-__device__ void rem_union_global(uint64_t *P, uint32_t x, uint32_t y) {
-    constexpr int S = __HIP_MEMORY_SCOPE_AGENT;
-    uint32_t rx = x, ry = y;
-    uint64_t px = aload<S>(P + rx);
-    uint64_t py = aload<S>(P + ry);
-    while (px != py) {
-        const bool xs = px > py;
-        const uint32_t n = xs ? rx : ry;
-        const uint64_t pn = xs ? px : py;
-        const uint64_t q = xs ? py : px;
-        const uint64_t seen = acas<S>(P + n, pn, q);
-        const bool ok = seen == pn;
-        if (ok && (uint32_t)pn == n)
-            return;
-        const uint32_t nn = ok ? (uint32_t)pn : n;
-        const uint64_t np = aload<S>(P + nn);
-        rx = xs ? nn : rx;
-        px = xs ? np : px;
-        ry = xs ? ry : nn;
-        py = xs ? py : np;
-    }
-}
+// (The unions of the scan and of the boundary merge run this step inside
+// their own flat per-lane loops; on the global array the entries are packed
+// (key of parent << 32 | parent id), so comparing packed parents compares
+// their keys and every set's root is the node with the smallest key.)
 
 // Find with full path compression, used only after all unions are done (the
 // root is fixed and the only value ever stored is the root's).
@@ -224,25 +180,6 @@ __device__ int32_t find_compress(int32_t *P, int32_t x) {
         int32_t nx = aload<S>(P + y);
         astore<S>(P + y, r);
         y = nx;
-    }
-    return r;
-}
-
-__device__ uint32_t find_compress_global(uint64_t *P, uint32_t x) {
-    constexpr int S = __HIP_MEMORY_SCOPE_AGENT;
-    uint32_t r = x;
-    uint64_t v;
-    for (;;) {
-        v = aload<S>(P + r);
-        if ((uint32_t)v == r)
-            break;
-        r = (uint32_t)v;
-    }
-    uint32_t y = x;
-    while (y != r) {
-        uint64_t nv = aload<S>(P + y);
-        astore<S>(P + y, v);
-        y = (uint32_t)nv;
     }
     return r;
 }
