@@ -1115,13 +1115,13 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
     // flat loop: every lane walks its components' parent chains one load per
     // iteration, without waiting for other lanes' longer chains; the walk's
     // end (the root entry) is written back to the component's own entry.
-    // All unions are done (previous kernel), so plain cached loads suffice:
-    // an entry read before another workgroup's write-back still points up
-    // the same tree, and roots never change here.
+    // The entries were last changed by device-scope atomics of the merge, so
+    // they are read at device scope too (a cached copy in this XCD's L2 may
+    // predate the merge).
     int j = tid;
     uint32_t r = (uint32_t)(cbase + j);
     while (j < n) {
-        const uint64_t v = im.uf[r];
+        const uint64_t v = aload<__HIP_MEMORY_SCOPE_AGENT>(im.uf + r);
         if ((uint32_t)v != r) {
             r = (uint32_t)v;
             continue;
@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
         const uint32_t id = (uint32_t)(cbase + j);
         const bool is = r == id;
         if (!is)
-            im.uf[id] = v;
+            astore<__HIP_MEMORY_SCOPE_AGENT>(im.uf + id, v);
         im.broot[id] = is;
         if (is) {
             const int key = im.bkey[id];
@@ -1247,7 +1247,7 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
                 gcf[c] = 1 + rowbase[key / TW] + im.bval[id];
                 atomicOr(&RM[key >> 5], 1u << (key & 31));
             } else {
-                const uint32_t rid = (uint32_t)im.uf[id];
+                const uint32_t rid = (uint32_t)aload<__HIP_MEMORY_SCOPE_AGENT>(im.uf + id);
                 gcf[c] = 1 + segment_base<NSR, TW, BH>(im, (int)(rid / G::CAP), im.bkey[rid]) + im.bval[rid];
             }
         } else {
