@@ -160,25 +160,32 @@ int get_workspace(hipStream_t stream, size_t need, void **out) {
     return CCL_OK;
 }
 
+// Sets a pointer field of an Img (whose device view is in the global
+// address space) from a device address.
+template <class P>
+static void set_ptr(P &field, const void *p) {
+    field = (P)(uintptr_t)p;
+}
+
 // Fill an Img from a descriptor, its layout and its workspace base.
 Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
     Img im{};
-    im.img = d.img;
-    im.labels = d.labels;
-    im.ncomp = d.num_components;
-    im.masks = reinterpret_cast<uint32_t *>(base + L.masks);
-    im.rt = reinterpret_cast<uint16_t *>(base + L.rt);
-    im.cb = reinterpret_cast<uint32_t *>(base + L.cb);
-    im.cf = reinterpret_cast<int32_t *>(base + L.cf);
-    im.tcnt = reinterpret_cast<int32_t *>(base + L.tcnt);
-    im.he = reinterpret_cast<uint16_t *>(base + L.he);
-    im.ve = reinterpret_cast<uint16_t *>(base + L.ve);
-    im.uf = reinterpret_cast<uint64_t *>(base + L.uf);
-    im.bval = reinterpret_cast<int32_t *>(base + L.bval);
-    im.bkey = reinterpret_cast<uint16_t *>(base + L.bkey);
-    im.broot = reinterpret_cast<uint8_t *>(base + L.broot);
-    im.seg = reinterpret_cast<int32_t *>(base + L.seg);
-    im.blk = reinterpret_cast<int32_t *>(base + L.blk);
+    set_ptr(im.img, d.img);
+    set_ptr(im.labels, d.labels);
+    set_ptr(im.ncomp, d.num_components);
+    set_ptr(im.masks, base + L.masks);
+    set_ptr(im.rt, base + L.rt);
+    set_ptr(im.cb, base + L.cb);
+    set_ptr(im.cf, base + L.cf);
+    set_ptr(im.tcnt, base + L.tcnt);
+    set_ptr(im.he, base + L.he);
+    set_ptr(im.ve, base + L.ve);
+    set_ptr(im.uf, base + L.uf);
+    set_ptr(im.bval, base + L.bval);
+    set_ptr(im.bkey, base + L.bkey);
+    set_ptr(im.broot, base + L.broot);
+    set_ptr(im.seg, base + L.seg);
+    set_ptr(im.blk, base + L.blk);
     im.stride = d.stride;
     im.H = (int32_t)d.H;
     im.W = (int32_t)d.W;

@@ -43,24 +43,35 @@ constexpr int kScanChunk = 4096;     // segment counts per scan block (256 x 16)
 // to the caller, the rest lives in the library workspace.  NT = NTY * NTX
 // tiles; RCAP, RW, CAP and NM are per-tile capacities fixed by the tile
 // shape (see Geo).
+// In the device pass the data pointers are typed as global-address-space
+// pointers (they all address device memory), so that the compiler emits
+// global rather than flat instructions: a flat access also counts in the LDS
+// wait counter, and every LDS wait would then wait for the stores in flight.
+// The host pass sees plain pointers of the same size and layout.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CCL_GLOBAL __attribute__((address_space(1)))
+#else
+#define CCL_GLOBAL
+#endif
 struct Img {
-    const uint8_t *img;   // H rows, pitch `stride` bytes
-    int32_t *labels;      // H x W, pitch W
-    int32_t *ncomp;       // optional K output (device)
-    uint32_t *masks;      // [NT][NM]    foreground bitmask of each tile
-    uint16_t *rt;         // [NT][RCAP]  local component of each node
-    uint32_t *cb;         // [NT][RW]    local component touches a shared tile edge (bit)
-    int32_t *cf;          // [NT][RCAP]  canonical key (local pixel index) of each local component,
-                          //             replaced by its final label by the component-label kernel
-    int32_t *tcnt;        // [NT][4]     nodes, components, boundary components
-    uint16_t *he;         // [NTY][2][hep] boundary index of each top(0)/bottom(1) tile-row pixel
-    uint16_t *ve;         // [NTX][2][vep] same for the left(0)/right(1) tile columns
-    uint64_t *uf;         // [NT][CAP]   global union-find: (key of parent << 32) | parent id
-    int32_t *bval;        // [NT][CAP]   interior roots before it in its row -> offset -> final label
-    uint16_t *bkey;       // [NT][CAP]   canonical key of boundary component j
-    uint8_t *broot;       // [NT][CAP]   boundary component j is its set's root
-    int32_t *seg;         // [H][NTX]    roots per (row, tile column) segment -> exclusive scan
-    int32_t *blk;         // [nblk]      scan block totals -> exclusive scan
+    CCL_GLOBAL const uint8_t *img;   // H rows, pitch `stride` bytes
+    CCL_GLOBAL int32_t *labels;      // H x W, pitch W
+    CCL_GLOBAL int32_t *ncomp;       // optional K output (device)
+    CCL_GLOBAL uint32_t *masks;      // [NT][NM]    foreground bitmask of each tile
+    CCL_GLOBAL uint16_t *rt;         // [NT][RCAP]  local component of each node
+    CCL_GLOBAL uint32_t *cb;         // [NT][RW]    local component touches a shared tile edge (bit)
+    CCL_GLOBAL int32_t *cf;          // [NT][RCAP]  canonical key (local pixel index) of each local
+                                     //             component, replaced by its final label by the
+                                     //             component-label kernel
+    CCL_GLOBAL int32_t *tcnt;        // [NT][4]     nodes, components, boundary components
+    CCL_GLOBAL uint16_t *he;         // [NTY][2][hep] boundary index of each top(0)/bottom(1) tile-row pixel
+    CCL_GLOBAL uint16_t *ve;         // [NTX][2][vep] same for the left(0)/right(1) tile columns
+    CCL_GLOBAL uint64_t *uf;         // [NT][CAP]   global union-find: (key of parent << 32) | parent id
+    CCL_GLOBAL int32_t *bval;        // [NT][CAP]   interior roots before it in its row -> offset -> final label
+    CCL_GLOBAL uint16_t *bkey;       // [NT][CAP]   canonical key of boundary component j
+    CCL_GLOBAL uint8_t *broot;       // [NT][CAP]   boundary component j is its set's root
+    CCL_GLOBAL int32_t *seg;         // [H][NTX]    roots per (row, tile column) segment -> exclusive scan
+    CCL_GLOBAL int32_t *blk;         // [nblk]      scan block totals -> exclusive scan
     int64_t stride;
     int32_t H, W, NTY, NTX, conn;
     int32_t level;        // foreground iff byte > level (0..255; 0 = nonzero)
@@ -79,23 +90,35 @@ struct Batch {
 
 enum Key { kTile = 0, kEdge = 1, kScan = 2 };
 
-__device__ __forceinline__ int32_t key_of(const Img &im, int which) {
-    return which == kTile ? im.tile0 : (which == kEdge ? im.edge0 : im.scan0);
-}
-
 // Image owning global work item `item` (binary search over the start keys).
-__device__ __forceinline__ const Img &find_img(const Batch &b, int32_t item, int which) {
+// Returned by value: the table is read through the constant address space
+// (it is written by the host before the launch and never by a kernel), so
+// the fields arrive by scalar loads, not vector loads that would be counted
+// together with the kernel's own stores.
+typedef __attribute__((address_space(4))) const Img ConstImg;
+
+__device__ __forceinline__ Img find_img(const Batch &b, int32_t item, int which) {
     if (b.n == 1)
         return b.one;
+    const ConstImg *tab = (const ConstImg *)(uintptr_t)b.tab;
     int lo = 0, hi = b.n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (key_of(b.tab[mid], which) <= item)
+        const int32_t k = which == kTile ? tab[mid].tile0 : (which == kEdge ? tab[mid].edge0 : tab[mid].scan0);
+        if (k <= item)
             lo = mid;
         else
             hi = mid - 1;
     }
-    return b.tab[lo];
+    static_assert(sizeof(Img) % 4 == 0, "image descriptor copied as words");
+    typedef __attribute__((address_space(4))) const uint32_t ConstWord;
+    const ConstWord *src = (const ConstWord *)(tab + lo);
+    Img r;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Img) / 4); i++)
+        dst[i] = src[i];
+    return r;
 }
 
 // Workgroups are dealt to the eight XCDs round robin (workgroup b runs on
@@ -138,17 +161,18 @@ struct Geo {
 // global array: the L2 caches of the eight XCDs are not coherent with each
 // other, so every access to a shared parent entry is an agent-scope atomic).
 // ------------------------------------------------------------------------
-template <int S, class T>
-__device__ __forceinline__ T aload(T *p) {
+// (P may carry an address space; V is the plain value type.)
+template <int S, class P>
+__device__ __forceinline__ auto aload(P *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, S);
 }
-template <int S, class T>
-__device__ __forceinline__ void astore(T *p, T v) {
+template <int S, class P, class V>
+__device__ __forceinline__ void astore(P *p, V v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
 }
 // Compare-and-swap; returns the value found at *p (== expect on success).
-template <int S, class T>
-__device__ __forceinline__ T acas(T *p, T expect, T v) {
+template <int S, class P, class V>
+__device__ __forceinline__ V acas(P *p, V expect, V v) {
     __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
     return expect;
 }
@@ -329,7 +353,9 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *tota
     return before + incl - v;
 }
 
-// Exclusive popcount prefix of n bitmask words (n may exceed NT).
+// Exclusive popcount prefix of n bitmask words (n may exceed NT).  pref is
+// written after the last barrier: a caller that reads entries written by
+// other waves needs a barrier first.
 template <int NT>
 __device__ __forceinline__ int32_t popcount_prefix(const uint32_t *bits, int32_t *pref, int n) {
     int32_t carry = 0;
@@ -449,8 +475,10 @@ struct ScanLds : RunLds<NSR, TW, BH> {
     static_assert(!GRAY || sizeof(BY) <= sizeof(ScanLate<NSR, TW, BH>), "gray tile layout");
 };
 
+// Eight waves per SIMD (four workgroups per CU, as the LDS allows): the
+// register allocator is held to the matching scalar-register budget.
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kTileThreads) void k_tile_scan(Batch b) {
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_scan(Batch b) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
     constexpr int NT = kTileThreads;
@@ -1115,13 +1143,13 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
     // flat loop: every lane walks its components' parent chains one load per
     // iteration, without waiting for other lanes' longer chains; the walk's
     // end (the root entry) is written back to the component's own entry.
-    // The entries were last changed by device-scope atomics of the merge, so
-    // they are read at device scope too (a cached copy in this XCD's L2 may
-    // predate the merge).
+    // All unions are done (previous kernel), so plain loads suffice: an entry
+    // read before another workgroup's write-back still points up the same
+    // tree, and roots never change here.
     int j = tid;
     uint32_t r = (uint32_t)(cbase + j);
     while (j < n) {
-        const uint64_t v = aload<__HIP_MEMORY_SCOPE_AGENT>(im.uf + r);
+        const uint64_t v = im.uf[r];
         if ((uint32_t)v != r) {
             r = (uint32_t)v;
             continue;
@@ -1129,7 +1157,7 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
         const uint32_t id = (uint32_t)(cbase + j);
         const bool is = r == id;
         if (!is)
-            astore<__HIP_MEMORY_SCOPE_AGENT>(im.uf + id, v);
+            im.uf[id] = v;
         im.broot[id] = is;
         if (is) {
             const int key = im.bkey[id];
@@ -1235,6 +1263,7 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
         rowbase[r] = (y0 + r < im.H) ? segment_base<NSR, TW, BH>(im, ti, r * TW) : 0;
     __syncthreads();
     popcount_prefix<kThreads>(BFB, BFP, ncw);
+    __syncthreads();  // BFP is read below by other waves than the ones that wrote it
     // each slot holds the component's key until this kernel writes its label
     int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
     const int32_t *gck = gcf;
@@ -1247,7 +1276,7 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
                 gcf[c] = 1 + rowbase[key / TW] + im.bval[id];
                 atomicOr(&RM[key >> 5], 1u << (key & 31));
             } else {
-                const uint32_t rid = (uint32_t)aload<__HIP_MEMORY_SCOPE_AGENT>(im.uf + id);
+                const uint32_t rid = (uint32_t)im.uf[id];
                 gcf[c] = 1 + segment_base<NSR, TW, BH>(im, (int)(rid / G::CAP), im.bkey[rid]) + im.bval[rid];
             }
         } else {

@@ -80,6 +80,16 @@ def test_every_tile_shape(ccl, conn):
         assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("name", inputs.ADVERSARIAL)
+def test_every_tile_shape_adversarial(ccl, name):
+    """Worst-case node and contact counts (checkerboard, stripes, combs) in
+    every tile configuration, including the ones that run 1024 threads."""
+    img = inputs.adversarial(name, 600, 1100, device=DEV)
+    for tile in range(1, len(ccl.tile_configs()) + 1):
+        for conn in (8, 4):
+            check(ccl, img, conn, tile=tile, what=f"{name} tile sweep")
+
+
 @pytest.mark.parametrize("p", [0.3, 0.407, 0.593, 0.7])
 def test_percolation_and_grf(ccl, p):
     img = inputs.bernoulli(1024, 1536, p, seed=11, device=DEV)
