@@ -287,9 +287,16 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     pm.mark();
     hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_relabel<NSR, TW, BH>),
-                       dim3((uint32_t)std::min<int64_t>(tiles, persistent_groups<k_relabel<NSR, TW, BH>>(kTileThreads))),
-                       dim3(kTileThreads), 0, s, b, (int32_t)tiles);
+    if (b.vec)
+        hipLaunchKernelGGL((k_relabel<NSR, TW, BH, true>),
+                           dim3((uint32_t)std::min<int64_t>(tiles,
+                                                            persistent_groups<k_relabel<NSR, TW, BH, true>>(kTileThreads))),
+                           dim3(kTileThreads), 0, s, b, (int32_t)tiles);
+    else
+        hipLaunchKernelGGL((k_relabel<NSR, TW, BH, false>),
+                           dim3((uint32_t)std::min<int64_t>(tiles,
+                                                            persistent_groups<k_relabel<NSR, TW, BH, false>>(kTileThreads))),
+                           dim3(kTileThreads), 0, s, b, (int32_t)tiles);
     pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
@@ -340,6 +347,12 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
     }
     Batch b{};
     b.n = n;
+    b.vec = 1;
+    for (int k = 0; k < n; k++) {
+        const ccl_image_desc &d = descs[idx[k]];
+        if (d.W % 4 != 0 || d.W > kVecMaxW || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0)
+            b.vec = 0;
+    }
     if (n == 1) {
         b.one = tab[0];
         b.tab = nullptr;

@@ -86,7 +86,9 @@ struct Batch {
     const Img *tab;  // device table of n images (n > 1)
     Img one;         // the image when n == 1
     int32_t n;
+    int32_t vec;     // every image: W % 4 == 0, labels 16-byte aligned, W <= kVecMaxW
 };
+constexpr int32_t kVecMaxW = 1 << 22;  // keeps a tile's row offsets in bytes below 2^31
 
 enum Key { kTile = 0, kEdge = 1, kScan = 2 };
 
@@ -1306,7 +1308,18 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
     uint32_t E[GRAY ? G::NM : 1];  // gray levels: same value as the left neighbour
 };
 
-template <int NSR, int TW, int BH>
+// Label stores of one tile row (VEC form: W % 4 == 0, 16-byte aligned
+// labels).  Buffer stores with the tile's first row as base: a lane whose
+// group lies right of the image, or whose row lies below it, gets an offset
+// past the buffer's size and its store is dropped by the hardware.  Every
+// wave so issues the same, fixed number of stores per tile, with no branch
+// around them, so the compiler can wait for the next tile's table loads
+// (issued before the stores) without waiting for the stores too.
+typedef __attribute__((address_space(4))) const int32_t ConstI32;
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer (gfx9 descriptor word 3)
+constexpr uint32_t kDropped = 0x80000000u;  // offset past every buffer this kernel builds (>= its size)
+
+template <int NSR, int TW, int BH, bool VEC>
 __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
@@ -1317,15 +1330,15 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     // load) and components; a tile with more nodes or components loads the
     // rest when it is labeled (rare: dense noise has ~1/10 of the capacity)
     constexpr int PJ = G::RB == 2 ? 2 : 3, CJ = G::RB == 2 ? 1 : 2;
+    static_assert(CJ * NT <= G::RCAP, "prefetched component slots lie in the table");
     __shared__ RelabelLds<NSR, TW, BH> t;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     // Persistent: each workgroup walks tiles blockIdx.x, +gridDim.x, ...
-    // While a tile's stores drain, the next tile's mask and tables are
-    // already in flight into registers, and the node and component counts
-    // of the tile after it (which size those table loads) too, so no load
-    // waits on another.  Few registers are held for this, so that four
-    // workgroups fit a CU.
+    // While a tile's labels are stored, the next tile's mask and tables are
+    // already in flight into registers; they move into LDS once every wave
+    // is done with the current tile.  The node and component counts (which
+    // size the table loads) are read one tile further ahead, by scalar loads.
     uint32_t pm[MPT];
     uint32_t pe[GRAY ? MPT : 1];
     uint32_t prt[PJ];   // node pairs 2q, 2q+1 (q = tid + j * NT): components, packed
@@ -1335,9 +1348,9 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     auto counts = [&](int tile) {
         if (tile < ntiles) {
             const Img &im = find_img(b, tile, kTile);
-            const int ti = tile - im.tile0;
-            qn_runs = im.tcnt[ti * 4 + 0];
-            qn_comp = im.tcnt[ti * 4 + 1];
+            const ConstI32 *tc = (const ConstI32 *)(uintptr_t)(im.tcnt + (tile - im.tile0) * 4);
+            qn_runs = tc[0];
+            qn_comp = tc[1];
         }
     };
     auto fetch = [&](int tile) {
@@ -1366,17 +1379,8 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
             pcf[j] = c < pn_comp ? gcf[c] : 0;
         }
     };
-    int tile = blockIdx.x;
-    if (tile < ntiles) {
-        counts(tile);
-        fetch(tile);
-        counts(tile + gridDim.x);
-    }
-    for (; tile < ntiles; tile += gridDim.x) {
-        const Img &im = find_img(b, tile, kTile);
-        const int ti = tile - im.tile0;
-        const int ty = ti / im.NTX, tx = ti % im.NTX;
-        const int y0 = ty * TH, x0 = tx * TW;
+    // mask and component labels of `tile` from registers into LDS
+    auto stage = [&](int tile) {
 #pragma unroll
         for (int k = 0; k < MPT; k++) {
             const int i = tid + k * NT;
@@ -1386,18 +1390,32 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
                     t.E[i] = pe[k];
             }
         }
+        // unconditional (entries past the tile's components are unused), so
+        // that the wait for these loads, the youngest of the prefetch, is
+        // on every path and no later use of the prefetch waits again
 #pragma unroll
-        for (int j = 0; j < CJ; j++) {
-            const int c = tid + j * NT;
-            if (c < pn_comp)
-                t.CF[c] = pcf[j];
-        }
+        for (int j = 0; j < CJ; j++)
+            t.CF[tid + j * NT] = pcf[j];
         if (pn_comp > CJ * NT) {
-            const int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+            const Img &im = find_img(b, tile, kTile);
+            const int32_t *gcf = im.cf + (int64_t)(tile - im.tile0) * G::RCAP;
             for (int c = CJ * NT + tid; c < pn_comp; c += NT)
                 t.CF[c] = gcf[c];
         }
-        __syncthreads();
+    };
+    int tile = blockIdx.x;
+    if (tile >= ntiles)
+        return;
+    counts(tile);
+    fetch(tile);
+    counts(tile + gridDim.x);
+    stage(tile);
+    __syncthreads();
+    for (;;) {
+        const Img &im = find_img(b, tile, kTile);
+        const int ti = tile - im.tile0;
+        const int ty = ti / im.NTX, tx = ti % im.NTX;
+        const int y0 = ty * TH, x0 = tx * TW;
         number_runs<NSR, TW, BH, NT>(t, t.E);
 #pragma unroll
         for (int j = 0; j < PJ; j++) {
@@ -1413,47 +1431,70 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
                 t.RF[k] = t.CF[grt[k]];
         }
         __syncthreads();
-        if (tile + (int)gridDim.x < ntiles) {
-            fetch(tile + gridDim.x);
-            counts(tile + 2 * (int)gridDim.x);
+        const int next = tile + (int)gridDim.x;
+        if (next < ntiles) {
+            fetch(next);
+            counts(next + (int)gridDim.x);
         }
 
         // write: one tile row segment of 256 pixels per wave instruction
-        const bool vec_ok = ((im.W & 3) == 0) && ((reinterpret_cast<uintptr_t>(im.labels) & 15u) == 0);
-        for (int r = wave; r < TH; r += NT / 64) {
-            const int y = y0 + r;
-            if (y >= im.H)
-                break;
-            const int R = r / G::RB;
-            for (int q = lane; q < TW / 4; q += 64) {
-                const int c0 = q * 4, x = x0 + c0;
-                if (x >= im.W)
-                    continue;
-                const int w = c0 >> 5, b0 = c0 & 31;
-                const uint32_t m = t.M[r * NW + w] >> b0;
-                const uint32_t s = t.S[R * NW + w];
-                const int32_t bs = t.base[R * NW + w] - 1;
-                i32x4 o;
-                o.x = (m & 1u) ? t.RF[bs + __popc(s & mask_le(b0))] : 0;
-                o.y = (m & 2u) ? t.RF[bs + __popc(s & mask_le(b0 + 1))] : 0;
-                o.z = (m & 4u) ? t.RF[bs + __popc(s & mask_le(b0 + 2))] : 0;
-                o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
-                int32_t *dst = im.labels + (int64_t)y * im.W + x;
-                if (vec_ok && x + 4 <= im.W) {
-                    __builtin_nontemporal_store(o, reinterpret_cast<i32x4 *>(dst));
-                } else {
+        if (VEC) {
+            // size: the bytes from the tile's first row to the end of the
+            // image (rows below the image fall past it), at most kDropped
+            const int64_t left = (int64_t)(im.H - y0) * im.W * 4;
+            const uint32_t nrec = left < (int64_t)kDropped ? (uint32_t)left : kDropped;
+            const __amdgpu_buffer_rsrc_t rsrc =
+                __builtin_amdgcn_make_buffer_rsrc(im.labels + (int64_t)y0 * im.W, 0, (int)nrec, kBufferWord3);
+#pragma unroll
+            for (int r = wave; r < TH; r += NT / 64) {
+                const int R = r / G::RB;
+#pragma unroll
+                for (int q = lane; q < TW / 4; q += 64) {
+                    const int c0 = q * 4;
+                    const int w = c0 >> 5, b0 = c0 & 31;
+                    const uint32_t m = t.M[r * NW + w] >> b0;
+                    const uint32_t s = t.S[R * NW + w];
+                    const int32_t bs = t.base[R * NW + w] - 1;
+                    i32x4 o;
+                    o.x = (m & 1u) ? t.RF[bs + __popc(s & mask_le(b0))] : 0;
+                    o.y = (m & 2u) ? t.RF[bs + __popc(s & mask_le(b0 + 1))] : 0;
+                    o.z = (m & 4u) ? t.RF[bs + __popc(s & mask_le(b0 + 2))] : 0;
+                    o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
+                    const uint32_t off = x0 + c0 < im.W ? (uint32_t)((r * im.W + x0 + c0) * 4) : kDropped;
+                    __builtin_amdgcn_raw_buffer_store_b128(o, rsrc, (int)off, 0, 2 /* nontemporal */);
+                }
+            }
+        } else {
+            for (int r = wave; r < TH; r += NT / 64) {
+                const int y = y0 + r;
+                if (y >= im.H)
+                    break;
+                const int R = r / G::RB;
+                for (int q = lane; q < TW / 4; q += 64) {
+                    const int c0 = q * 4, x = x0 + c0;
+                    if (x >= im.W)
+                        continue;
+                    const int w = c0 >> 5, b0 = c0 & 31;
+                    const uint32_t m = t.M[r * NW + w] >> b0;
+                    const uint32_t s = t.S[R * NW + w];
+                    const int32_t bs = t.base[R * NW + w] - 1;
+                    int32_t o[4];
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        o[e] = ((m >> e) & 1u) ? t.RF[bs + __popc(s & mask_le(b0 + e))] : 0;
+                    int32_t *dst = im.labels + (int64_t)y * im.W + x;
                     const int nn = im.W - x < 4 ? im.W - x : 4;
-                    dst[0] = o.x;
-                    if (nn > 1)
-                        dst[1] = o.y;
-                    if (nn > 2)
-                        dst[2] = o.z;
-                    if (nn > 3)
-                        dst[3] = o.w;
+                    for (int e = 0; e < nn; e++)
+                        dst[e] = o[e];
                 }
             }
         }
+        if (next >= ntiles)
+            break;
         __syncthreads();
+        stage(next);
+        __syncthreads();
+        tile = next;
     }
 }
 

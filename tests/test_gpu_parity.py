@@ -117,6 +117,24 @@ def test_strided_unaligned_and_odd_width(ccl):
         check(ccl, narrow, conn, what="stride 64, W 37")
 
 
+@pytest.mark.parametrize("shape", [(285, 700), (31, 256), (33, 260), (65, 516), (100, 1000), (70, 73)])
+def test_no_writes_outside_labels(ccl, shape):
+    """The label array is written exactly: a guard band after it (and the
+    rows below a ragged last tile row) stays untouched."""
+    H, W = shape
+    img = inputs.bernoulli(H, W, 0.5, seed=H + W, device=DEV)
+    for conn in (8, 4):
+        guard = 1 << 20
+        big = torch.full((H * W + guard,), -7, dtype=torch.int32, device=DEV)
+        out = big[:H * W].view(H, W)
+        say(f"case guard band shape={shape} conn={conn}")
+        ccl.label(img, conn, out=out)
+        torch.cuda.synchronize()
+        ref, _ = oracle.cclremsp(img.cpu().numpy(), conn)
+        assert np.array_equal(out.cpu().numpy(), ref)
+        assert bool((big[H * W:] == -7).all())
+
+
 def test_nonzero_bytes_are_foreground(ccl):
     g = torch.Generator().manual_seed(0)
     vals = torch.randint(0, 256, (200, 333), generator=g, dtype=torch.int32)
