@@ -329,17 +329,25 @@ __device__ __forceinline__ uint32_t load_word(const Img &im, int y, int x) {
 
 // Exclusive prefix sum of v over a workgroup of NT threads; *total gets the
 // sum.  Contains two barriers; every thread must call it.
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes (lanes without a source add 0),
+// then the last lane of row 0 / 2 is added to row 1 / 3 and the last lane
+// of row 1 to rows 2 and 3.
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 template <int NT>
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
     __shared__ int32_t wsum[NT / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d)
-            incl += o;
-    }
+    const int32_t incl = wave_inclusive_scan(v);
     if (lane == 63)
         wsum[wv] = incl;
     __syncthreads();
