@@ -613,6 +613,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     // with more contacts than the list holds is done in several rounds.
     uint64_t cm1[UPT2];  // U1 positions (low half; partner at c) and U3 (high half; partner at c-1)
     uint32_t cm2[UPT2];  // U2 positions (partner at c+1)
+    uint64_t dm1[UPT2];  // first contact of a run starting in the word: direct link, same layout
+    uint32_t dm2[UPT2];
     int32_t coff[UPT2];
     int32_t n_pairs = 0;
 #pragma unroll
@@ -622,6 +624,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const int R = u / NW, w = u % NW;
         cm1[k] = 0;
         cm2[k] = 0u;
+        dm1[k] = 0;
+        dm2[k] = 0u;
         if (GRAY && h < LPU && R > 0) {
             // gray levels (one row per block row): U1 at the first column of
             // each stretch where the pixel above has the same value and both
@@ -659,15 +663,65 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                 u2 = m & ~mn & ~up & un;
                 u3 = m & ~mp & ~up & upp;
             }
+            // first contact of each run that starts in this word: the carry
+            // of (run bits without contacts) + (run starts) stops at it
+            const uint32_t B = block_mask<NSR, TW, BH>(t.M, R, w);
+            const uint32_t C = u1 | u2 | u3;
+            const uint32_t F = ((B & ~C) + t.S[u]) & C;
+            const uint32_t d3 = F & u3, d1 = F & ~u3 & u1, d2 = F & ~u3 & ~u1 & u2;
             // this thread's share of the word's contact positions
             constexpr int PART = 32 / LPU;
             const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
-            cm1[k] = (uint64_t)(u1 & mine) | ((uint64_t)(u3 & mine) << 32);
-            cm2[k] = u2 & mine;
+            cm1[k] = (uint64_t)(u1 & ~d1 & mine) | ((uint64_t)(u3 & ~d3 & mine) << 32);
+            cm2[k] = u2 & ~d2 & mine;
+            dm1[k] = (uint64_t)(d1 & mine) | ((uint64_t)(d3 & mine) << 32);
+            dm2[k] = d2 & mine;
         }
         int32_t tot;
         coff[k] = n_pairs + block_exclusive_scan<NT>(__popcll(cm1[k]) + __popc(cm2[k]), &tot);
         n_pairs += tot;
+    }
+    // direct links (the scan's copy step: a pixel whose first neighbour is
+    // found takes that neighbour's set without a merge): the first contact
+    // of each run makes the run's node a child of the upper node.  The node
+    // is still a fresh root and the upper node has the smaller ordinal, so
+    // parents stay below their children, as the Rem steps require; the run's
+    // further contacts are merged as before.
+#pragma unroll
+    for (int k = 0; k < UPT2; k++) {
+        uint64_t a = dm1[k];
+        uint32_t c2 = dm2[k];
+        if (!a && !c2)
+            continue;
+        const int u = (tid + k * NT) % G::NU;
+        const int w = u % NW;
+        const uint32_t sR = t.S[u];
+        const int32_t bR = t.base[u] - 1;
+        const int uu = u - NW;
+        const uint32_t sU = t.S[uu];
+        const int32_t bU = t.base[uu] - 1;
+        const uint32_t sUL = w ? t.S[uu - 1] : 0u;
+        const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
+        const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
+        const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
+        while (a || c2) {
+            int c, d;
+            if (a) {
+                const int bit = __ffsll((unsigned long long)a) - 1;
+                a &= a - 1;
+                c = bit & 31;
+                d = (bit >> 5) ? -1 : 0;
+            } else {
+                c = __ffs(c2) - 1;
+                c2 &= c2 - 1u;
+                d = 1;
+            }
+            const int32_t x = bR + __popc(sR & mask_le(c));
+            const int pc = c + d;
+            const uint32_t sp = pc < 0 ? sUL : (pc > 31 ? sUR : sU);
+            const int32_t bp = pc < 0 ? bUL : (pc > 31 ? bUR : bU);
+            t.P[x] = bp + __popc(sp & mask_le(pc & 31));
+        }
     }
     for (int r0 = 0; r0 < n_pairs; r0 += ScanLds<NSR, TW, BH>::PRCAP) {
         const int r1 = r0 + ScanLds<NSR, TW, BH>::PRCAP;
@@ -749,6 +803,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
         __syncthreads();
     }
+    __syncthreads();
     for (int i = tid; i < G::NM; i += NT)
         t.late.RK[i] = 0u;
     for (int r = tid; r < TH; r += NT)
