@@ -777,28 +777,24 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             rx = (int32_t)(pr & 0xFFFFu);
             ry = (int32_t)(pr >> 16);
         }
+        // Branch-free step: when both parents are equal the compare-and-swap
+        // puts the value onto itself and changes nothing.
         while (q < np) {
             const int32_t px = aload<WG>(t.P + rx);
             const int32_t py = aload<WG>(t.P + ry);
-            bool next = px == py;
-            if (!next) {
-                const bool xs = px > py;
-                const int32_t n = xs ? rx : ry;
-                const int32_t pn = xs ? px : py;
-                const int32_t seen = acas<WG>(t.P + n, pn, xs ? py : px);
-                if (seen == pn) {
-                    next = pn == n;
-                    rx = xs ? pn : rx;
-                    ry = xs ? ry : pn;
-                }
-            }
+            const bool xs = px > py;
+            const int32_t n = xs ? rx : ry;
+            const int32_t pn = xs ? px : py;
+            const int32_t seen = acas<WG>(t.P + n, pn, xs ? py : px);
+            const bool ok = seen == pn;
+            const bool next = px == py || (ok && pn == n);
+            rx = ok && xs ? pn : rx;
+            ry = ok && !xs ? pn : ry;
             if (next) {
                 q += NT;
-                if (q < np) {
-                    const uint32_t pr = t.PR[q];
-                    rx = (int32_t)(pr & 0xFFFFu);
-                    ry = (int32_t)(pr >> 16);
-                }
+                const uint32_t pr = t.PR[min(q, np - 1)];
+                rx = (int32_t)(pr & 0xFFFFu);
+                ry = (int32_t)(pr >> 16);
             }
         }
         __syncthreads();
