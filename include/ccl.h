@@ -97,7 +97,8 @@ int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn
 /*
  * ccl_label_ex -- as ccl_label, plus
  *   num_components  device int32 receiving K, or NULL.
- *   tile            tile configuration id from ccl_tile_config (0 = default).
+ *   tile            tile configuration id from ccl_tile_config (0 = the default
+ *                   for the image's kind, ccl_tile_default).
  */
 int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
                  int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
@@ -146,7 +147,8 @@ typedef struct {
  * for the whole batch (tiles of all images share each grid).
  *   descs   host array of n descriptors (copied during the call).
  *   n       number of images (0 is a no-op returning CCL_OK).
- *   tile    tile configuration id used for every image (0 = default).
+ *   tile    tile configuration id used for every image (0 = each image's
+ *           kind takes its default, ccl_tile_default).
  * Every descriptor is validated first; the first invalid one makes the call
  * return its error with nothing launched.
  */
@@ -170,7 +172,7 @@ int ccl_graph_launch(ccl_graph *graph, hipStream_t stream);
 int ccl_graph_destroy(ccl_graph *graph);
 
 /* Workspace bytes one ccl_label_ex call needs for an H x W image with the
- * given tile configuration (0 = default); 0 for invalid arguments.  Used for
+ * given tile configuration (0 = the kind's default); 0 for invalid arguments.  Used for
  * admission by HBM footprint: footprint = image + labels + workspace. */
 size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile);
 
@@ -187,15 +189,21 @@ int ccl_reserve(size_t bytes, hipStream_t stream);
  * device first). */
 int ccl_release(void);
 
-/* Tile configuration `id` (1-based; 0 = default) -> block rows and tile
- * width in pixels.  A tile is `block rows` x 2 image rows under
- * 8-connectivity with the row-pair scan (two rows at a time), `block rows`
- * x 1 with single rows (4-connectivity, CCL_SCAN_ROW), and `block rows` / 2
- * x 1 for gray levels (where every pixel may be its own run).  Returns
- * CCL_OK, or CCL_ERR_TILE when id is out of range.  ccl_tile_count() gives
- * the number of configurations. */
+/* Tile configuration `id` (1-based) -> block rows and tile width in
+ * pixels.  A tile is `block rows` x 2 image rows under 8-connectivity with
+ * the row-pair scan (two rows at a time), `block rows` x 1 with single rows
+ * (4-connectivity, CCL_SCAN_ROW), and `block rows` / 2 x 1 for gray levels
+ * (where every pixel may be its own run).  Returns CCL_OK, or CCL_ERR_TILE
+ * when id is out of range; id 0 reports configuration 1.  ccl_tile_count()
+ * gives the number of configurations. */
 int ccl_tile_config(int id, int *block_rows, int *tile_w);
 int ccl_tile_count(void);
+
+/* The configuration id that tile id 0 selects for an image of this kind
+ * (each kind of a batch takes its own): row pairs (conn 8, CCL_SCAN_PAIR),
+ * single rows (conn 4 or CCL_SCAN_ROW) and gray levels (gray = 1; the scan
+ * is then ignored) have separate defaults.  0 for invalid arguments. */
+int ccl_tile_default(int conn, int scan, int gray);
 
 /*
  * Phase timing.  ccl_profile(1) makes every later call record a HIP event on
@@ -240,7 +248,7 @@ typedef struct {
     int max_batch;              /* images per batch, >= 1 */
     int64_t max_batch_pixels;   /* pixels per batch (a larger single image still runs alone) */
     size_t hbm_budget;          /* device bytes of all slot workspaces together */
-    int tile;                   /* tile configuration id (0 = default) */
+    int tile;                   /* tile configuration id (0 = per-kind default) */
 } ccl_server_config;
 
 typedef struct {

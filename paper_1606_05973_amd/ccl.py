@@ -56,6 +56,8 @@ _lib.ccl_tile_config.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), cty
 _lib.ccl_tile_config.restype = ctypes.c_int
 _lib.ccl_tile_count.argtypes = []
 _lib.ccl_tile_count.restype = ctypes.c_int
+_lib.ccl_tile_default.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_lib.ccl_tile_default.restype = ctypes.c_int
 _lib.ccl_batch_graph_create.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_void_p)]
 _lib.ccl_batch_graph_create.restype = ctypes.c_int
@@ -146,8 +148,9 @@ def _img_geometry(img: torch.Tensor):
 
 
 def tile_configs():
-    """[(block_rows, tile_w)] for ids 1..n; id 0 means the default (id 1).
-    Tile height is block_rows * 2 under 8-connectivity, block_rows under 4."""
+    """[(block_rows, tile_w)] for ids 1..n; id 0 means each kind's default
+    (tile_default).  Tile height is block_rows * 2 under 8-connectivity,
+    block_rows under 4."""
     out = []
     for i in range(1, _lib.ccl_tile_count() + 1):
         h, w = ctypes.c_int(), ctypes.c_int()
@@ -249,10 +252,18 @@ def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Te
     return outs
 
 
+def tile_default(conn: int, scan: int = SCAN_PAIR, gray: bool = False) -> int:
+    """Configuration id that tile 0 selects for this kind of image."""
+    t = _lib.ccl_tile_default(int(conn), int(scan), int(bool(gray)))
+    if t <= 0:
+        raise ValueError("invalid conn / scan / gray")
+    return t
+
+
 def tile_shape(tile: int, conn: int, scan: int = SCAN_PAIR, gray: bool = False):
     """(tile height, tile width) in pixels of configuration `tile` for `conn`
     (gray-level tiles have half the block rows, one image row each)."""
-    nsr, tw = tile_configs()[max(tile, 1) - 1]
+    nsr, tw = tile_configs()[(tile if tile > 0 else tile_default(conn, scan, gray)) - 1]
     if gray:
         return nsr // 2, tw
     return nsr * (2 if conn == 8 and scan == SCAN_PAIR else 1), tw

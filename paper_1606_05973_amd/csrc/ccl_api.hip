@@ -25,6 +25,7 @@ namespace {
 // rows x 1 under 4-connectivity.  id 1 is the default.
 struct TileCfg {
     int nsr, tw;
+    bool dflt;   // asked for id 0: each launch group takes its own default
 };
 constexpr TileCfg kTiles[] = {{32, 256}, {16, 256}, {16, 512}, {64, 128}, {32, 128}, {8, 512}, {64, 256}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
@@ -37,6 +38,13 @@ inline int bh_of(const ccl_image_desc &d) { return d.gray ? 1 : bh_of(d.conn, d.
 // Launch groups of a batch: row-pair runs, single-row runs, gray levels.
 enum Group { kPair = 0, kRow = 1, kGray = 2, kGroups = 3 };
 inline int group_of(const ccl_image_desc &d) { return d.gray ? kGray : (bh_of(d) == 2 ? kPair : kRow); }
+inline int group_of(int conn, int scan, int gray) { return gray ? kGray : (bh_of(conn, scan) == 2 ? kPair : kRow); }
+
+// Default tile id per group (fastest in a sweep of the configurations on
+// 21568^2 images): row pairs 64x256 pixels, single rows 64x128, gray levels
+// 32x256.
+constexpr int kDefaultTile[kGroups] = {1, 4, 7};
+inline TileCfg tile_for(const TileCfg &c, int group) { return c.dflt ? kTiles[kDefaultTile[group] - 1] : c; }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
@@ -112,8 +120,11 @@ int check_opts(const ccl_image_desc &d) {
 }
 
 int resolve_tile(int tile, TileCfg *out) {
-    if (tile == 0)
-        tile = 1;
+    if (tile == 0) {
+        *out = kTiles[0];
+        out->dflt = true;
+        return CCL_OK;
+    }
     if (tile < 1 || tile > kNumTiles)
         return CCL_ERR_TILE;
     *out = kTiles[tile - 1];
@@ -362,14 +373,15 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
             return CCL_ERR_HIP;
         b.tab = dtab;
     }
-    return dispatch(c, group, b, tiles, edges, blocks, n, stream);
+    return dispatch(tile_for(c, group), group, b, tiles, edges, blocks, n, stream);
 }
 
 size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
                    std::vector<size_t> *offs) {
     size_t off = align_up((size_t)n * sizeof(Img));
     for (int i = 0; i < n; i++) {
-        Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), c, descs[i].gray != 0);
+        Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), tile_for(c, group_of(descs[i])),
+                             descs[i].gray != 0);
         if (lays)
             lays->push_back(L);
         if (offs)
@@ -674,6 +686,12 @@ int ccl_profile_read(double *ms, int nphase, int *ncalls) {
 
 int ccl_tile_count(void) { return kNumTiles; }
 
+int ccl_tile_default(int conn, int scan, int gray) {
+    if ((conn != 4 && conn != 8) || (scan != CCL_SCAN_PAIR && scan != CCL_SCAN_ROW) || (gray != 0 && gray != 1))
+        return 0;
+    return kDefaultTile[group_of(conn, scan, gray)];
+}
+
 int ccl_tile_config(int id, int *tile_h, int *tile_w) {
     TileCfg c;
     int st = resolve_tile(id, &c);
@@ -758,7 +776,7 @@ struct ccl_server {
     std::thread th;
 
     size_t bytes_of(const ccl_image_desc &d) const {
-        return ccl::layout_of(d.H, d.W, ccl::bh_of(d), tile, d.gray != 0).bytes;
+        return ccl::layout_of(d.H, d.W, ccl::bh_of(d), ccl::tile_for(tile, ccl::group_of(d)), d.gray != 0).bytes;
     }
 
     void finish(ccl::ServerSlot &sl, Clock::time_point now) {

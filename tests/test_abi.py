@@ -24,7 +24,7 @@ def test_header_declares_api():
     names = _declared_functions()
     for expected in ("ccl_label", "ccl_label_ex", "ccl_label_batch", "ccl_workspace_bytes",
                      "ccl_batch_workspace_bytes", "ccl_reserve", "ccl_release", "ccl_tile_config",
-                     "ccl_tile_count", "ccl_strerror", "ccl_batch_graph_create", "ccl_graph_launch",
+                     "ccl_tile_count", "ccl_tile_default", "ccl_strerror", "ccl_batch_graph_create", "ccl_graph_launch",
                      "ccl_graph_destroy", "ccl_profile", "ccl_profile_read"):
         assert expected in names
 
@@ -94,7 +94,13 @@ def test_strerror_and_tiles():
     assert tiles[0] == (32, 256) and len(tiles) == ccl._lib.ccl_tile_count()
     for nsr, tw in tiles:
         assert tw % 64 == 0 and 2 * nsr * tw < 65536
-    assert ccl.tile_shape(0, 8) == (64, 256) and ccl.tile_shape(0, 4) == (32, 256)
+    # id 0: each kind takes its own default
+    assert ccl.tile_default(8) == 1 and ccl.tile_default(4) == 4 and ccl.tile_default(8, ccl.SCAN_ROW) == 4
+    assert ccl.tile_default(8, gray=True) == 7 and ccl.tile_default(4, gray=True) == 7
+    assert ccl.tile_shape(0, 8) == (64, 256) and ccl.tile_shape(0, 4) == (64, 128)
+    assert ccl.tile_shape(0, 8, gray=True) == (32, 256)
+    for bad in ((6, 0, 0), (8, 2, 0), (8, 0, 2)):
+        assert ccl._lib.ccl_tile_default(*bad) == 0
 
 
 def test_workspace_bytes():
