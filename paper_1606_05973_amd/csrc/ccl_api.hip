@@ -290,13 +290,15 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     if (edges > 0)
         hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((edges + kThreads - 1) / kThreads)), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), dim3((uint32_t)((tiles + kWaves - 1) / kWaves)), blk, 0, s, b,
+                       (int32_t)tiles);
     pm.mark();
     hipLaunchKernelGGL(k_scan_blocks, dim3((uint32_t)blocks), blk, 0, s, b);
     pm.mark();
     hipLaunchKernelGGL(k_scan_top, dim3((uint32_t)nimg), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)tiles), blk, 0, s, b);
+    hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)((tiles + kWaves - 1) / kWaves)), blk, 0, s,
+                       b, (int32_t)tiles);
     pm.mark();
     if (b.vec)
         hipLaunchKernelGGL((k_relabel<NSR, TW, BH, true>),

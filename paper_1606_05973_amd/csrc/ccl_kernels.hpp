@@ -35,6 +35,7 @@
 namespace ccl {
 
 constexpr int kThreads = 256;       // threads per workgroup of the small kernels (4 wave64)
+constexpr int kWaves = kThreads / 64;  // tiles per workgroup where one wave handles a tile
 constexpr int kTileThreads = 512;   // threads per workgroup of the tile scan and labeling pass (8 wave64)
 constexpr uint16_t kNone = 0xFFFFu;  // background pixel in the edge buffers
 constexpr int kScanChunk = 4096;     // segment counts per scan block (256 x 16)
@@ -361,6 +362,30 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *tota
     __syncthreads();
     *total = all;
     return before + incl - v;
+}
+
+// LDS written by some lanes of a wave, then read by others: keeps the
+// compiler from moving LDS accesses across this point (a wave's LDS
+// operations are carried out in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exclusive popcount prefix of n bitmask words by one whole wave (all 64
+// lanes call it); returns the total.
+__device__ __forceinline__ int32_t wave_popcount_prefix(const uint32_t *bits, int32_t *pref, int n, int lane) {
+    int32_t carry = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int i = base + lane;
+        const int32_t v = i < n ? __popc(bits[i]) : 0;
+        const int32_t incl = wave_inclusive_scan(v);
+        if (i < n)
+            pref[i] = carry + incl - v;
+        carry += __builtin_amdgcn_readlane(incl, 63);
+    }
+    return carry;
 }
 
 // Exclusive popcount prefix of n bitmask words (n may exceed NT).  pref is
@@ -1179,27 +1204,34 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
 // K3a: flatten the boundary components of one tile; a component that is its
 // set's root owns the set's first raster pixel.  Adds those roots to the
 // segment counts and turns their "interior roots before" into the offset
-// inside their row segment.
+// inside their row segment.  One wave per tile (kWaves tiles per
+// workgroup): the kernel is bound by the latency of its dependent loads, so
+// many tiles in flight matter more than many lanes per tile.
 // ------------------------------------------------------------------------
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
+__global__ __launch_bounds__(kThreads) void k_flatten(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr int NW = G::NW, TH = G::TH;
-    __shared__ uint32_t RK[G::NM];
-    __shared__ int32_t rowc[TH];
-    const Img &im = find_img(b, blockIdx.x, kTile);
-    const int ti = blockIdx.x - im.tile0;
+    __shared__ uint32_t RKs[kWaves][G::NM];
+    __shared__ int32_t rowcs[kWaves][TH];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * kWaves + wv;
+    if (tile >= ntiles)
+        return;
+    const Img &im = find_img(b, tile, kTile);
+    const int ti = tile - im.tile0;
     const int n = im.tcnt[ti * 4 + 2];
     if (n == 0)
         return;
+    uint32_t *RK = RKs[wv];
+    int32_t *rowc = rowcs[wv];
     const int ty = ti / im.NTX, tx = ti % im.NTX;
     const int y0 = ty * TH;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < G::NM; i += kThreads)
+    for (int i = lane; i < G::NM; i += 64)
         RK[i] = 0u;
-    for (int r = tid; r < TH; r += kThreads)
+    for (int r = lane; r < TH; r += 64)
         rowc[r] = 0;
-    __syncthreads();
+    wave_sync();
     const int64_t cbase = (int64_t)ti * G::CAP;
     // flat loop: every lane walks its components' parent chains one load per
     // iteration, without waiting for other lanes' longer chains; the walk's
@@ -1207,7 +1239,7 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
     // All unions are done (previous kernel), so plain loads suffice: an entry
     // read before another workgroup's write-back still points up the same
     // tree, and roots never change here.
-    int j = tid;
+    int j = lane;
     uint32_t r = (uint32_t)(cbase + j);
     while (j < n) {
         const uint64_t v = im.uf[r];
@@ -1225,18 +1257,18 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b) {
             atomicOr(&RK[key >> 5], 1u << (key & 31));
             atomicAdd(&rowc[key / TW], 1);
         }
-        j += kThreads;
+        j += 64;
         r = (uint32_t)(cbase + j);
     }
-    __syncthreads();
-    for (int j = tid; j < n; j += kThreads) {
+    wave_sync();
+    for (int j = lane; j < n; j += 64) {
         const uint32_t id = (uint32_t)(cbase + j);
         if (im.broot[id]) {
             const int key = im.bkey[id];
             im.bval[id] += popc_before(&RK[(key / TW) * NW], key % TW);
         }
     }
-    for (int r = tid; r < TH; r += kThreads)
+    for (int r = lane; r < TH; r += 64)
         if (rowc[r] && y0 + r < im.H)
             im.seg[(int64_t)(y0 + r) * im.NTX + tx] += rowc[r];
 }
@@ -1290,7 +1322,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(Batch b) {
 //   inside the segment (both known after K3a and K4), computable from any
 //   tile, so a non-root boundary component reads its root's entries
 //   directly; interior components are ranked inside their row segment
-//   among the segment's roots (interior and boundary).
+//   among the segment's roots (interior and boundary).  One wave per tile,
+//   as in K3a.
 // ------------------------------------------------------------------------
 template <int NSR, int TW, int BH>
 __device__ __forceinline__ int32_t segment_base(const Img &im, int tile, int key) {
@@ -1301,35 +1334,40 @@ __device__ __forceinline__ int32_t segment_base(const Img &im, int tile, int key
 }
 
 template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
+__global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr int NW = G::NW, TH = G::TH;
-    __shared__ uint32_t BFB[G::RW];
-    __shared__ int32_t BFP[G::RW];
-    __shared__ uint32_t RM[G::NM];   // keys of the segment roots (bit per pixel)
-    __shared__ int32_t rowbase[TH];
-    const Img &im = find_img(b, blockIdx.x, kTile);
-    const int ti = blockIdx.x - im.tile0;
+    __shared__ uint32_t BFBs[kWaves][G::RW];
+    __shared__ int32_t BFPs[kWaves][G::RW];
+    __shared__ uint32_t RMs[kWaves][G::NM];   // keys of the segment roots (bit per pixel)
+    __shared__ int32_t rowbases[kWaves][TH];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * kWaves + wv;
+    if (tile >= ntiles)
+        return;
+    uint32_t *BFB = BFBs[wv], *RM = RMs[wv];
+    int32_t *BFP = BFPs[wv], *rowbase = rowbases[wv];
+    const Img &im = find_img(b, tile, kTile);
+    const int ti = tile - im.tile0;
     const int ty = ti / im.NTX;
     const int y0 = ty * TH;
-    const int tid = threadIdx.x;
     const int n_comp = im.tcnt[ti * 4 + 1];
     const int ncw = (n_comp + 31) >> 5;
     const uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
-    for (int i = tid; i < ncw; i += kThreads)
+    for (int i = lane; i < ncw; i += 64)
         BFB[i] = gcb[i];
-    for (int i = tid; i < G::NM; i += kThreads)
+    for (int i = lane; i < G::NM; i += 64)
         RM[i] = 0u;
-    for (int r = tid; r < TH; r += kThreads)
+    for (int r = lane; r < TH; r += 64)
         rowbase[r] = (y0 + r < im.H) ? segment_base<NSR, TW, BH>(im, ti, r * TW) : 0;
-    __syncthreads();
-    popcount_prefix<kThreads>(BFB, BFP, ncw);
-    __syncthreads();  // BFP is read below by other waves than the ones that wrote it
+    wave_sync();
+    wave_popcount_prefix(BFB, BFP, ncw, lane);
+    wave_sync();
     // each slot holds the component's key until this kernel writes its label
     int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
     const int32_t *gck = gcf;
     const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int c = tid; c < n_comp; c += kThreads) {
+    for (int c = lane; c < n_comp; c += 64) {
         const int key = gck[c];
         if ((BFB[c >> 5] >> (c & 31)) & 1u) {
             const uint32_t id = (uint32_t)(cbase + rank_of(BFB, BFP, c));
@@ -1344,8 +1382,8 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b) {
             atomicOr(&RM[key >> 5], 1u << (key & 31));
         }
     }
-    __syncthreads();
-    for (int c = tid; c < n_comp; c += kThreads) {
+    wave_sync();
+    for (int c = lane; c < n_comp; c += 64) {
         if (!((BFB[c >> 5] >> (c & 31)) & 1u)) {
             const int key = gck[c], kr = key / TW;
             gcf[c] = 1 + rowbase[kr] + popc_before(&RM[kr * NW], key % TW);
