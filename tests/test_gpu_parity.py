@@ -124,15 +124,18 @@ def test_no_writes_outside_labels(ccl, shape):
     H, W = shape
     img = inputs.bernoulli(H, W, 0.5, seed=H + W, device=DEV)
     for conn in (8, 4):
-        guard = 1 << 20
-        big = torch.full((H * W + guard,), -7, dtype=torch.int32, device=DEV)
-        out = big[:H * W].view(H, W)
-        say(f"case guard band shape={shape} conn={conn}")
-        ccl.label(img, conn, out=out)
-        torch.cuda.synchronize()
-        ref, _ = oracle.cclremsp(img.cpu().numpy(), conn)
-        assert np.array_equal(out.cpu().numpy(), ref)
-        assert bool((big[H * W:] == -7).all())
+        # offset 0: 16-byte aligned rows when W % 4 == 0 (vector stores);
+        # offset 1: the label array starts 4 bytes into the buffer (plain stores)
+        for off in (0, 1):
+            guard = 1 << 20
+            big = torch.full((off + H * W + guard,), -7, dtype=torch.int32, device=DEV)
+            out = big[off:off + H * W].view(H, W)
+            say(f"case guard band shape={shape} conn={conn} offset={off}")
+            ccl.label(img, conn, out=out)
+            torch.cuda.synchronize()
+            ref, _ = oracle.cclremsp(img.cpu().numpy(), conn)
+            assert np.array_equal(out.cpu().numpy(), ref)
+            assert bool((big[:off] == -7).all()) and bool((big[off + H * W:] == -7).all())
 
 
 def test_nonzero_bytes_are_foreground(ccl):
