@@ -1367,8 +1367,9 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b, int32_t ntile
     int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
     const int32_t *gck = gcf;
     const int64_t cbase = (int64_t)ti * G::CAP;
-    for (int c = lane; c < n_comp; c += 64) {
-        const int key = gck[c];
+    // boundary components: label from the scan (roots) or from the root's
+    // entries; every root's key goes into RM
+    auto first = [&](int c, int key) {
         if ((BFB[c >> 5] >> (c & 31)) & 1u) {
             const uint32_t id = (uint32_t)(cbase + rank_of(BFB, BFP, c));
             if (im.broot[id]) {
@@ -1381,14 +1382,40 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b, int32_t ntile
         } else {
             atomicOr(&RM[key >> 5], 1u << (key & 31));
         }
-    }
-    wave_sync();
-    for (int c = lane; c < n_comp; c += 64) {
+    };
+    // interior components: ranked among the roots of their row segment
+    auto second = [&](int c, int key) {
         if (!((BFB[c >> 5] >> (c & 31)) & 1u)) {
-            const int key = gck[c], kr = key / TW;
+            const int kr = key / TW;
             gcf[c] = 1 + rowbase[kr] + popc_before(&RM[kr * NW], key % TW);
         }
+    };
+    // the keys of a lane's first KR components are loaded at once and kept
+    // in registers for both passes (more overlap of the load latency)
+    constexpr int KR = 8;
+    int32_t kreg[KR];
+#pragma unroll
+    for (int i = 0; i < KR; i++) {
+        const int c = lane + i * 64;
+        kreg[i] = c < n_comp ? gck[c] : 0;
     }
+#pragma unroll
+    for (int i = 0; i < KR; i++) {
+        const int c = lane + i * 64;
+        if (c < n_comp)
+            first(c, kreg[i]);
+    }
+    for (int c = lane + KR * 64; c < n_comp; c += 64)
+        first(c, gck[c]);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < KR; i++) {
+        const int c = lane + i * 64;
+        if (c < n_comp)
+            second(c, kreg[i]);
+    }
+    for (int c = lane + KR * 64; c < n_comp; c += 64)
+        second(c, gck[c]);
 }
 
 // ------------------------------------------------------------------------
