@@ -300,16 +300,17 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)((tiles + kWaves - 1) / kWaves)), blk, 0, s,
                        b, (int32_t)tiles);
     pm.mark();
-    if (b.vec)
-        hipLaunchKernelGGL((k_relabel<NSR, TW, BH, true>),
-                           dim3((uint32_t)std::min<int64_t>(tiles,
-                                                            persistent_groups<k_relabel<NSR, TW, BH, true>>(kTileThreads))),
-                           dim3(kTileThreads), 0, s, b, (int32_t)tiles);
+#define CCL_RELABEL(F_)                                                                                     \
+    hipLaunchKernelGGL((k_relabel<NSR, TW, BH, F_>),                                                        \
+                       dim3((uint32_t)std::min<int64_t>(tiles, persistent_groups<k_relabel<NSR, TW, BH, F_>>(kTileThreads))), \
+                       dim3(kTileThreads), 0, s, b, (int32_t)tiles)
+    if (b.store == kStore16)
+        CCL_RELABEL(kStore16);
+    else if (b.store == kStore4)
+        CCL_RELABEL(kStore4);
     else
-        hipLaunchKernelGGL((k_relabel<NSR, TW, BH, false>),
-                           dim3((uint32_t)std::min<int64_t>(tiles,
-                                                            persistent_groups<k_relabel<NSR, TW, BH, false>>(kTileThreads))),
-                           dim3(kTileThreads), 0, s, b, (int32_t)tiles);
+        CCL_RELABEL(kStoreAny);
+#undef CCL_RELABEL
     pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
@@ -360,11 +361,13 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
     }
     Batch b{};
     b.n = n;
-    b.vec = 1;
+    b.store = kStore16;
     for (int k = 0; k < n; k++) {
         const ccl_image_desc &d = descs[idx[k]];
-        if (d.W % 4 != 0 || d.W > kVecMaxW || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0)
-            b.vec = 0;
+        if (d.W > kVecMaxW)
+            b.store = kStoreAny;
+        else if (b.store == kStore16 && (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0))
+            b.store = kStore4;
     }
     if (n == 1) {
         b.one = tab[0];

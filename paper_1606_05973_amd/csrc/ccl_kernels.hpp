@@ -87,7 +87,7 @@ struct Batch {
     const Img *tab;  // device table of n images (n > 1)
     Img one;         // the image when n == 1
     int32_t n;
-    int32_t vec;     // every image: W % 4 == 0, labels 16-byte aligned, W <= kVecMaxW
+    int32_t store;   // labeling-pass store form (StoreForm) that suits every image
 };
 constexpr int32_t kVecMaxW = 1 << 22;  // keeps a tile's row offsets in bytes below 2^31
 
@@ -1432,18 +1432,25 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
     uint32_t E[GRAY ? G::NM : 1];  // gray levels: same value as the left neighbour
 };
 
-// Label stores of one tile row (VEC form: W % 4 == 0, 16-byte aligned
-// labels).  Buffer stores with the tile's first row as base: a lane whose
-// group lies right of the image, or whose row lies below it, gets an offset
-// past the buffer's size and its store is dropped by the hardware.  Every
-// wave so issues the same, fixed number of stores per tile, with no branch
-// around them, so the compiler can wait for the next tile's table loads
-// (issued before the stores) without waiting for the stores too.
+// Label stores.  Buffer stores with the tile's first row as base: a lane
+// whose pixels lie right of the image, or whose row lies below it, gets an
+// offset past the buffer's size and its store is dropped by the hardware.
+// Every wave so issues the same, fixed number of stores per tile, with no
+// branch around them, so the compiler can wait for the next tile's table
+// loads (issued before the stores) without waiting for the stores too.
+//   kStore16: W % 4 == 0 and 16-byte aligned labels; one 16-byte store per
+//             lane covers four adjacent pixels.
+//   kStore4:  any width; four 4-byte stores per lane, lane L taking pixels
+//             L, L + 64, ... of the row segment, so that each store
+//             instruction writes 64 adjacent pixels.
+//   kStoreAny: plain stores (images wider than kVecMaxW).
 typedef __attribute__((address_space(4))) const int32_t ConstI32;
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer (gfx9 descriptor word 3)
 constexpr uint32_t kDropped = 0x80000000u;  // offset past every buffer this kernel builds (>= its size)
 
-template <int NSR, int TW, int BH, bool VEC>
+enum StoreForm { kStoreAny = 0, kStore4 = 1, kStore16 = 2 };
+
+template <int NSR, int TW, int BH, int STORE>
 __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
@@ -1562,13 +1569,13 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         }
 
         // write: one tile row segment of 256 pixels per wave instruction
-        if (VEC) {
-            // size: the bytes from the tile's first row to the end of the
-            // image (rows below the image fall past it), at most kDropped
-            const int64_t left = (int64_t)(im.H - y0) * im.W * 4;
-            const uint32_t nrec = left < (int64_t)kDropped ? (uint32_t)left : kDropped;
-            const __amdgpu_buffer_rsrc_t rsrc =
-                __builtin_amdgcn_make_buffer_rsrc(im.labels + (int64_t)y0 * im.W, 0, (int)nrec, kBufferWord3);
+        // buffer size: the bytes from the tile's first row to the end of
+        // the image (rows below the image fall past it), at most kDropped
+        const int64_t left = (int64_t)(im.H - y0) * im.W * 4;
+        const uint32_t nrec = left < (int64_t)kDropped ? (uint32_t)left : kDropped;
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc(im.labels + (int64_t)y0 * im.W, 0, (int)nrec, kBufferWord3);
+        if (STORE == kStore16) {
 #pragma unroll
             for (int r = wave; r < TH; r += NT / 64) {
                 const int R = r / G::RB;
@@ -1586,6 +1593,21 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
                     o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
                     const uint32_t off = x0 + c0 < im.W ? (uint32_t)((r * im.W + x0 + c0) * 4) : kDropped;
                     __builtin_amdgcn_raw_buffer_store_b128(o, rsrc, (int)off, 0, 2 /* nontemporal */);
+                }
+            }
+        } else if (STORE == kStore4) {
+#pragma unroll
+            for (int r = wave; r < TH; r += NT / 64) {
+                const int R = r / G::RB;
+#pragma unroll
+                for (int e = 0; e < TW / 64; e++) {
+                    const int c = e * 64 + lane;
+                    const int w = c >> 5, b0 = c & 31;
+                    const bool fg = (t.M[r * NW + w] >> b0) & 1u;
+                    const int32_t v =
+                        fg ? t.RF[t.base[R * NW + w] - 1 + __popc(t.S[R * NW + w] & mask_le(b0))] : 0;
+                    const uint32_t off = x0 + c < im.W ? (uint32_t)((r * im.W + x0 + c) * 4) : kDropped;
+                    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, (int)off, 0, 2 /* nontemporal */);
                 }
             }
         } else {
