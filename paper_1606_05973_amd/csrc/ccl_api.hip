@@ -335,17 +335,17 @@ int dispatch(const TileCfg &c, int group, const Batch &b, int64_t tiles, int64_t
 
 // Images with the same rows per block row share every launch; a batch
 // mixing them runs as two such groups, one after the other on the stream.
-// Workspace: [tables of both groups][per-image regions].  The group's table
-// is built in `htab` (pinned host memory that stays untouched until the
-// stream has passed the copy) or, when htab is NULL, in a temporary.
-int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
-              const std::vector<size_t> &offs, char *base, Img *dtab, int group, const TileCfg &c,
-              hipStream_t stream, bool table_ready = false, Img *htab = nullptr) {
+// Table of a group of n images: n Img entries, then the n tile0, n edge0
+// and n scan0 keys as a compact array (searched by find_img).
+size_t group_table_bytes(size_t n) { return align_up(n * (sizeof(Img) + 3 * sizeof(int32_t))); }
+
+// Fills a group's table (Img entries and keys) in `tab`; returns the counts.
+int build_group_table(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+                      const std::vector<size_t> &offs, char *base, char *tab_bytes, int64_t *tiles_out,
+                      int64_t *edges_out, int64_t *blocks_out) {
     const int n = (int)idx.size();
-    if (n == 0)
-        return CCL_OK;
-    std::vector<Img> local(htab ? 0 : n);
-    Img *tab = htab ? htab : local.data();
+    Img *tab = reinterpret_cast<Img *>(tab_bytes);
+    int32_t *keys = reinterpret_cast<int32_t *>(tab_bytes + (size_t)n * sizeof(Img));
     int64_t tiles = 0, edges = 0, blocks = 0;
     for (int k = 0; k < n; k++) {
         const int i = idx[k];
@@ -353,12 +353,38 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
         tab[k].tile0 = (int32_t)tiles;
         tab[k].edge0 = (int32_t)edges;
         tab[k].scan0 = (int32_t)blocks;
+        keys[k] = tab[k].tile0;
+        keys[n + k] = tab[k].edge0;
+        keys[2 * n + k] = tab[k].scan0;
         tiles += lays[i].NT;
         edges += lays[i].nedge;
         blocks += lays[i].nblk;
         if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
             return CCL_ERR_TOO_LARGE;
     }
+    *tiles_out = tiles;
+    *edges_out = edges;
+    *blocks_out = blocks;
+    return CCL_OK;
+}
+
+// Workspace: [tables of the groups][per-image regions].  The group's table
+// is built in `htab` (pinned host memory that stays untouched until the
+// stream has passed the copy) or, when htab is NULL, in a temporary.
+int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+              const std::vector<size_t> &offs, char *base, char *dtab, int group, const TileCfg &c,
+              hipStream_t stream, bool table_ready = false, char *htab = nullptr) {
+    const int n = (int)idx.size();
+    if (n == 0)
+        return CCL_OK;
+    const size_t tbytes = group_table_bytes((size_t)n);
+    std::vector<char> local(htab ? 0 : tbytes);
+    char *tab_bytes = htab ? htab : local.data();
+    const Img *tab = reinterpret_cast<const Img *>(tab_bytes);
+    int64_t tiles = 0, edges = 0, blocks = 0;
+    int st = build_group_table(descs, idx, lays, offs, base, tab_bytes, &tiles, &edges, &blocks);
+    if (st != CCL_OK)
+        return st;
     Batch b{};
     b.n = n;
     b.store = kStore16;
@@ -372,18 +398,24 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
     if (n == 1) {
         b.one = tab[0];
         b.tab = nullptr;
+        b.keys = nullptr;
     } else {
-        if (!table_ready &&
-            hipMemcpyAsync(dtab, tab, (size_t)n * sizeof(Img), hipMemcpyHostToDevice, stream) != hipSuccess)
+        if (!table_ready && hipMemcpyAsync(dtab, tab_bytes, tbytes, hipMemcpyHostToDevice, stream) != hipSuccess)
             return CCL_ERR_HIP;
-        b.tab = dtab;
+        b.tab = reinterpret_cast<const Img *>(dtab);
+        b.keys = reinterpret_cast<const int32_t *>(dtab + (size_t)n * sizeof(Img));
     }
     return dispatch(tile_for(c, group), group, b, tiles, edges, blocks, n, stream);
 }
 
 size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
                    std::vector<size_t> *offs) {
-    size_t off = align_up((size_t)n * sizeof(Img));
+    size_t per_group[kGroups] = {0, 0, 0};
+    for (int i = 0; i < n; i++)
+        per_group[group_of(descs[i])]++;
+    size_t off = 0;
+    for (int k = 0; k < kGroups; k++)
+        off += group_table_bytes(per_group[k]);
     for (int i = 0; i < n; i++) {
         Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), tile_for(c, group_of(descs[i])),
                              descs[i].gray != 0);
@@ -398,21 +430,20 @@ size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::ve
 
 // Launch a batch into a workspace of at least batch_bytes(descs) bytes.
 int run_batch_in(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream, char *base,
-                 Img *htab = nullptr) {
+                 char *htab = nullptr) {
     std::vector<Layout> lays;
     std::vector<size_t> offs;
     batch_bytes(descs, n, c, &lays, &offs);
     std::vector<int> g[kGroups];
     for (int i = 0; i < n; i++)
         g[group_of(descs[i])].push_back(i);
-    Img *dtab = reinterpret_cast<Img *>(base);
     size_t at = 0;
     for (int k = 0; k < kGroups; k++) {
-        const int st = run_group(descs, g[k], lays, offs, base, dtab + at, k, c, stream, false,
+        const int st = run_group(descs, g[k], lays, offs, base, base + at, k, c, stream, false,
                                  htab ? htab + at : nullptr);
         if (st != CCL_OK)
             return st;
-        at += g[k].size();
+        at += group_table_bytes(g[k].size());
     }
     return CCL_OK;
 }
@@ -427,24 +458,16 @@ int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t 
 
 // Device table of one group, uploaded synchronously (used before capture).
 int upload_group_table(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
-                       const std::vector<size_t> &offs, char *base, Img *dtab) {
+                       const std::vector<size_t> &offs, char *base, char *dtab) {
     const int n = (int)idx.size();
     if (n <= 1)
         return CCL_OK;
-    std::vector<Img> tab(n);
+    std::vector<char> tab(group_table_bytes((size_t)n));
     int64_t tiles = 0, edges = 0, blocks = 0;
-    for (int k = 0; k < n; k++) {
-        const int i = idx[k];
-        tab[k] = make_img(descs[i], lays[i], base + offs[i]);
-        tab[k].tile0 = (int32_t)tiles;
-        tab[k].edge0 = (int32_t)edges;
-        tab[k].scan0 = (int32_t)blocks;
-        tiles += lays[i].NT;
-        edges += lays[i].nedge;
-        blocks += lays[i].nblk;
-    }
-    return hipMemcpy(dtab, tab.data(), (size_t)n * sizeof(Img), hipMemcpyHostToDevice) == hipSuccess ? CCL_OK
-                                                                                                     : CCL_ERR_HIP;
+    const int st = build_group_table(descs, idx, lays, offs, base, tab.data(), &tiles, &edges, &blocks);
+    if (st != CCL_OK)
+        return st;
+    return hipMemcpy(dtab, tab.data(), tab.size(), hipMemcpyHostToDevice) == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
 
 }  // namespace
@@ -572,10 +595,10 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
     std::vector<int> grp[kGroups];
     for (int i = 0; i < n; i++)
         grp[group_of(descs[i])].push_back(i);
-    Img *dtab = reinterpret_cast<Img *>(base);
-    size_t at[kGroups] = {0, grp[0].size(), grp[0].size() + grp[1].size()};
+    size_t at[kGroups] = {0, group_table_bytes(grp[0].size()),
+                          group_table_bytes(grp[0].size()) + group_table_bytes(grp[1].size())};
     for (int k = 0; k < kGroups && st == CCL_OK; k++)
-        st = upload_group_table(descs, grp[k], lays, offs, base, dtab + at[k]);
+        st = upload_group_table(descs, grp[k], lays, offs, base, base + at[k]);
     hipStream_t cs = nullptr;
     if (st == CCL_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
         st = CCL_ERR_HIP;
@@ -585,7 +608,7 @@ int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_gra
         } else {
             int s2 = CCL_OK;
             for (int k = 0; k < kGroups && s2 == CCL_OK; k++)
-                s2 = run_group(descs, grp[k], lays, offs, base, dtab + at[k], k, c, cs, true);
+                s2 = run_group(descs, grp[k], lays, offs, base, base + at[k], k, c, cs, true);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &graph);
             st = s2 != CCL_OK ? s2 : (e == hipSuccess ? CCL_OK : CCL_ERR_HIP);
@@ -752,7 +775,7 @@ struct ServerReq {
 struct ServerSlot {
     hipStream_t stream = nullptr;
     char *ws = nullptr;      // device workspace of ws_bytes
-    Img *htab = nullptr;     // pinned host image table (max_batch entries)
+    char *htab = nullptr;    // pinned host image tables (for up to max_batch images)
     hipEvent_t done = nullptr;
     std::vector<ServerReq> batch;
     bool busy = false;
@@ -901,8 +924,8 @@ int ccl_server_create(const ccl_server_config *cfg, ccl_server **out) {
     for (auto &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&sl.htab), (size_t)cfg->max_batch * sizeof(ccl::Img)) !=
-                hipSuccess)
+            hipHostMalloc(reinterpret_cast<void **>(&sl.htab),
+                          ccl::group_table_bytes((size_t)cfg->max_batch) * ccl::kGroups) != hipSuccess)
             st = CCL_ERR_HIP;
         else if (hipMalloc(reinterpret_cast<void **>(&sl.ws), s->ws_bytes) != hipSuccess)
             st = CCL_ERR_NOMEM;

@@ -84,8 +84,9 @@ struct Img {
 };
 
 struct Batch {
-    const Img *tab;  // device table of n images (n > 1)
-    Img one;         // the image when n == 1
+    const Img *tab;         // device table of n images (n > 1)
+    const int32_t *keys;    // n tile0, then n edge0, then n scan0 of the table (n > 1)
+    Img one;                // the image when n == 1
     int32_t n;
     int32_t store;   // labeling-pass store form (StoreForm) that suits every image
 };
@@ -100,15 +101,18 @@ enum Key { kTile = 0, kEdge = 1, kScan = 2 };
 // together with the kernel's own stores.
 typedef __attribute__((address_space(4))) const Img ConstImg;
 
+// The search runs over a compact array of start keys, whose few cache lines
+// stay in the scalar cache.
 __device__ __forceinline__ Img find_img(const Batch &b, int32_t item, int which) {
     if (b.n == 1)
         return b.one;
     const ConstImg *tab = (const ConstImg *)(uintptr_t)b.tab;
+    typedef __attribute__((address_space(4))) const int32_t ConstKey;
+    const ConstKey *key = (const ConstKey *)(uintptr_t)(b.keys + (int64_t)which * b.n);
     int lo = 0, hi = b.n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        const int32_t k = which == kTile ? tab[mid].tile0 : (which == kEdge ? tab[mid].edge0 : tab[mid].scan0);
-        if (k <= item)
+        if (key[mid] <= item)
             lo = mid;
         else
             hi = mid - 1;
