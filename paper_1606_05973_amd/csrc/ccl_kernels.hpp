@@ -1444,9 +1444,14 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
 // loads (issued before the stores) without waiting for the stores too.
 //   kStore16: W % 4 == 0 and 16-byte aligned labels; one 16-byte store per
 //             lane covers four adjacent pixels.
-//   kStore4:  any width; four 4-byte stores per lane, lane L taking pixels
-//             L, L + 64, ... of the row segment, so that each store
-//             instruction writes 64 adjacent pixels.
+//   kStore4:  any width or alignment; four 4-byte stores per lane, lane L
+//             taking pixels L, L + 64, ... of the row segment, so that each
+//             store instruction writes 64 adjacent pixels.  Plain (cached)
+//             stores: a row segment that does not start on a cache line
+//             shares its first and last lines with the neighbouring tiles,
+//             which the workgroups of the same XCD label at the same time,
+//             and the L2 merges the parts (nontemporal partial lines were
+//             1.4x slower).
 //   kStoreAny: plain stores (images wider than kVecMaxW).
 typedef __attribute__((address_space(4))) const int32_t ConstI32;
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer (gfx9 descriptor word 3)
@@ -1480,15 +1485,17 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     int32_t pcf[CJ];
     int pn_runs = 0, pn_comp = 0;   // counts of the tile whose tables are in registers
     int qn_runs = 0, qn_comp = 0;   // counts of the tile after it
-    auto counts = [&](int tile) {
-        if (tile < ntiles) {
+    auto counts = [&](int slot) {
+        if (slot < ntiles) {
+            const int tile = xcd_tile(slot, ntiles);
             const Img &im = find_img(b, tile, kTile);
             const ConstI32 *tc = (const ConstI32 *)(uintptr_t)(im.tcnt + (tile - im.tile0) * 4);
             qn_runs = tc[0];
             qn_comp = tc[1];
         }
     };
-    auto fetch = [&](int tile) {
+    auto fetch = [&](int slot) {
+        const int tile = xcd_tile(slot, ntiles);
         const Img &im = find_img(b, tile, kTile);
         const int ti = tile - im.tile0;
         pn_runs = qn_runs;
@@ -1515,7 +1522,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         }
     };
     // mask and component labels of `tile` from registers into LDS
-    auto stage = [&](int tile) {
+    auto stage = [&](int slot) {
 #pragma unroll
         for (int k = 0; k < MPT; k++) {
             const int i = tid + k * NT;
@@ -1532,21 +1539,27 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         for (int j = 0; j < CJ; j++)
             t.CF[tid + j * NT] = pcf[j];
         if (pn_comp > CJ * NT) {
+            const int tile = xcd_tile(slot, ntiles);
             const Img &im = find_img(b, tile, kTile);
             const int32_t *gcf = im.cf + (int64_t)(tile - im.tile0) * G::RCAP;
             for (int c = CJ * NT + tid; c < pn_comp; c += NT)
                 t.CF[c] = gcf[c];
         }
     };
-    int tile = blockIdx.x;
-    if (tile >= ntiles)
+    // slots blockIdx.x, + gridDim.x, ...; slot i is tile xcd_tile(i), so that
+    // the workgroups of one XCD label neighbouring tiles at the same time
+    // (their label rows share cache lines where a row segment is not
+    // 64-byte aligned)
+    int slot = blockIdx.x;
+    if (slot >= ntiles)
         return;
-    counts(tile);
-    fetch(tile);
-    counts(tile + gridDim.x);
-    stage(tile);
+    counts(slot);
+    fetch(slot);
+    counts(slot + gridDim.x);
+    stage(slot);
     __syncthreads();
     for (;;) {
+        const int tile = xcd_tile(slot, ntiles);
         const Img &im = find_img(b, tile, kTile);
         const int ti = tile - im.tile0;
         const int ty = ti / im.NTX, tx = ti % im.NTX;
@@ -1566,7 +1579,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
                 t.RF[k] = t.CF[grt[k]];
         }
         __syncthreads();
-        const int next = tile + (int)gridDim.x;
+        const int next = slot + (int)gridDim.x;
         if (next < ntiles) {
             fetch(next);
             counts(next + (int)gridDim.x);
@@ -1611,7 +1624,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
                     const int32_t v =
                         fg ? t.RF[t.base[R * NW + w] - 1 + __popc(t.S[R * NW + w] & mask_le(b0))] : 0;
                     const uint32_t off = x0 + c < im.W ? (uint32_t)((r * im.W + x0 + c) * 4) : kDropped;
-                    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, (int)off, 0, 2 /* nontemporal */);
+                    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, (int)off, 0, 0 /* cached */);
                 }
             }
         } else {
@@ -1644,7 +1657,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         __syncthreads();
         stage(next);
         __syncthreads();
-        tile = next;
+        slot = next;
     }
 }
 
