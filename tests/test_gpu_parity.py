@@ -138,6 +138,15 @@ def test_no_writes_outside_labels(ccl, shape):
             assert bool((big[:off] == -7).all()) and bool((big[off + H * W:] == -7).all())
 
 
+@pytest.mark.parametrize("W", [(1 << 22), (1 << 22) + 4, (1 << 22) + 1])
+def test_very_wide_rows(ccl, W):
+    """Rows up to 4 Mi pixels take the buffer-store forms of the labeling
+    pass, wider rows the plain stores; all must agree with the oracle."""
+    img = inputs.bernoulli(3, W, 0.5, seed=W, device=DEV)
+    for conn in (8, 4):
+        check(ccl, img, conn, what=f"very wide W={W}")
+
+
 def test_nonzero_bytes_are_foreground(ccl):
     g = torch.Generator().manual_seed(0)
     vals = torch.randint(0, 256, (200, 333), generator=g, dtype=torch.int32)
