@@ -1485,9 +1485,10 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     int32_t pcf[CJ];
     int pn_runs = 0, pn_comp = 0;   // counts of the tile whose tables are in registers
     int qn_runs = 0, qn_comp = 0;   // counts of the tile after it
+    auto tile_of = [&](int slot) { return STORE == kStore4 ? xcd_tile(slot, ntiles) : slot; };
     auto counts = [&](int slot) {
         if (slot < ntiles) {
-            const int tile = xcd_tile(slot, ntiles);
+            const int tile = tile_of(slot);
             const Img &im = find_img(b, tile, kTile);
             const ConstI32 *tc = (const ConstI32 *)(uintptr_t)(im.tcnt + (tile - im.tile0) * 4);
             qn_runs = tc[0];
@@ -1495,7 +1496,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         }
     };
     auto fetch = [&](int slot) {
-        const int tile = xcd_tile(slot, ntiles);
+        const int tile = tile_of(slot);
         const Img &im = find_img(b, tile, kTile);
         const int ti = tile - im.tile0;
         pn_runs = qn_runs;
@@ -1539,17 +1540,18 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         for (int j = 0; j < CJ; j++)
             t.CF[tid + j * NT] = pcf[j];
         if (pn_comp > CJ * NT) {
-            const int tile = xcd_tile(slot, ntiles);
+            const int tile = tile_of(slot);
             const Img &im = find_img(b, tile, kTile);
             const int32_t *gcf = im.cf + (int64_t)(tile - im.tile0) * G::RCAP;
             for (int c = CJ * NT + tid; c < pn_comp; c += NT)
                 t.CF[c] = gcf[c];
         }
     };
-    // slots blockIdx.x, + gridDim.x, ...; slot i is tile xcd_tile(i), so that
-    // the workgroups of one XCD label neighbouring tiles at the same time
-    // (their label rows share cache lines where a row segment is not
-    // 64-byte aligned)
+    // slots blockIdx.x, + gridDim.x, ...; with the 4-byte store form slot i
+    // is tile xcd_tile(i), so that the workgroups of one XCD label
+    // neighbouring tiles at the same time (their label rows share cache
+    // lines where a row segment is not line aligned); aligned rows keep the
+    // plain order (slightly faster there)
     int slot = blockIdx.x;
     if (slot >= ntiles)
         return;
@@ -1559,7 +1561,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     stage(slot);
     __syncthreads();
     for (;;) {
-        const int tile = xcd_tile(slot, ntiles);
+        const int tile = tile_of(slot);
         const Img &im = find_img(b, tile, kTile);
         const int ti = tile - im.tile0;
         const int ty = ti / im.NTX, tx = ti % im.NTX;
