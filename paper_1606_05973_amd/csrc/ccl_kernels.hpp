@@ -1069,6 +1069,27 @@ __device__ __forceinline__ uint32_t line_byte(const Img &im, bool horiz, int fix
     return horiz ? im.img[(int64_t)fixed * im.stride + pos] : im.img[(int64_t)pos * im.stride + fixed];
 }
 
+// Gray levels: the 32 bytes at positions from..from+31 of an edge line (row
+// `fixed` for a horizontal edge, column `fixed` for a vertical one) as 8
+// dwords; 0 outside the image.
+__device__ __forceinline__ void line_bytes(const Img &im, bool horiz, int fixed, int from, uint32_t *d) {
+    if (horiz) {
+        load_bytes(im, fixed, from, d);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        uint32_t w = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int pos = from + 4 * j + q;
+            if (pos < im.H)
+                w |= (uint32_t)im.img[(int64_t)pos * im.stride + fixed] << (8 * q);
+        }
+        d[j] = w;
+    }
+}
+
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     using G = Geo<NSR, TW, BH>;
@@ -1128,22 +1149,23 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
         // gray levels: object pixels face each other across the edge and
         // connect when their bytes are equal; every such position is a
         // contact (repeats of one component pair are skipped below)
+        // The 32 bytes of each line are loaded at once (independent loads),
+        // then compared four at a time: the later line with the earlier one
+        // at c, c - 1 and c + 1.
         const int lo_fixed = horiz ? later_t * TH : later_t * TW;
-        uint32_t v = 0u, d1 = 0u, d2 = 0u;
-        uint32_t hp = line_byte(im, horiz, lo_fixed - 1, from - 1, n);
-        uint32_t hc = line_byte(im, horiz, lo_fixed - 1, from, n);
-        for (int c = 0; c < 32; c++) {
-            const uint32_t hn = line_byte(im, horiz, lo_fixed - 1, from + c + 1, n);
-            if ((m >> c) & 1u) {
-                const uint32_t lv = line_byte(im, horiz, lo_fixed, from + c, n);
-                v |= (uint32_t)(lv == hc) << c;
-                d1 |= (uint32_t)(lv == hp) << c;
-                d2 |= (uint32_t)(lv == hn) << c;
-            }
-            hp = hc;
-            hc = hn;
+        uint32_t lb[8], hb[8], sp[8], sn[8];
+        line_bytes(im, horiz, lo_fixed, from, lb);
+        line_bytes(im, horiz, lo_fixed - 1, from, hb);
+        const uint32_t hprev = line_byte(im, horiz, lo_fixed - 1, from - 1, n);
+        const uint32_t hnext = line_byte(im, horiz, lo_fixed - 1, from + 32, n);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            sp[j] = (hb[j] << 8) | (j ? hb[j - 1] >> 24 : hprev);              // byte c: earlier line at c - 1
+            sn[j] = (hb[j] >> 8) | ((j < 7 ? hb[j + 1] : hnext) << 24);        // byte c: earlier line at c + 1
         }
-        // (an equal byte is an object pixel too, since the levels match)
+        const uint32_t v = m & eq32(lb, hb), d1 = m & eq32(lb, sp), d2 = m & eq32(lb, sn);
+        // (an equal byte is an object pixel too, since the levels match; a
+        // position outside the image reads 0, which no object byte equals)
         cm1 = (uint64_t)v | (conn8 ? ((uint64_t)(d1 & (from > 0 ? 0xFFFFFFFFu : 0xFFFFFFFEu)) << 32) : 0ull);
         cm2 = conn8 ? d2 : 0u;
     }
