@@ -31,7 +31,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E peak, GB/s
 BYTES_PER_PX = 5            # compulsory: 1 B image read + 4 B int32 label write
-# algorithmic bytes per pixel of each phase's launch
+# algorithmic bytes per pixel of each phase's launch: the tile scan reads the
+# image (1 B/px); the labeling pass writes the labels (4 B/px) and reads the
+# image information once more, as a 1-bit mask in place of the bytes (1 B/px)
 PHASE_BYTES_PER_PX = {"tile_scan": 1.0, "labeling_pass": 5.0}
 METRIC = "Gpixel/s and % of HBM roofline, 8-conn, bit-exact; batched/served vs single"
 
