@@ -913,33 +913,32 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
 
     // 6. components touching an edge shared with another tile
     const bool top = ty > 0, bot = ty < im.NTY - 1, left = tx > 0, right = tx < im.NTX - 1;
-    for (int i = tid; i < 2 * NW + 2 * TH; i += NT) {
-        if (i < 2 * NW) {
-            const int side = i / NW, w = i % NW;
-            if ((side == 0 && !top) || (side == 1 && !bot))
-                continue;
-            const int r = side ? TH - 1 : 0, R = r / G::RB;
-            uint32_t starts;
+    // one item per pixel of the top and bottom rows (marked where a run of
+    // the row starts) and of the left and right columns
+    for (int i = tid; i < 2 * TW + 2 * TH; i += NT) {
+        int r, c;
+        bool on;
+        if (i < 2 * TW) {
+            const int side = i / TW;
+            c = i % TW;
+            r = side ? TH - 1 : 0;
+            const int w = c >> 5, bt = c & 31;
+            bool start;
             if (G::RB == 1) {
-                starts = t.S[r * NW + w];   // run starts of the row itself
+                start = (t.S[r * NW + w] >> bt) & 1u;   // run starts of the row itself
             } else {
                 const uint32_t m = t.M[r * NW + w];
-                const uint32_t mL = w ? t.M[r * NW + w - 1] : 0u;
-                starts = m & ~((m << 1) | (mL >> 31));
+                const uint32_t prev = bt ? (m >> (bt - 1)) & 1u : (w ? t.M[r * NW + w - 1] >> 31 : 0u);
+                start = ((m >> bt) & 1u) && !prev;
             }
-            while (starts) {
-                const int bb = __ffs(starts) - 1;
-                starts &= starts - 1u;
-                const int32_t comp = t.late.RT[node_at(t, R, (w << 5) + bb)];
-                atomicOr(&t.late.RFB[comp >> 5], 1u << (comp & 31));
-            }
+            on = (side ? bot : top) && start;
         } else {
-            const int q = i - 2 * NW, side = q / TH, r = q % TH;
-            if ((side == 0 && !left) || (side == 1 && !right))
-                continue;
-            const int c = side ? TW - 1 : 0;
-            if (!((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u))
-                continue;
+            const int q = i - 2 * TW, side = q / TH;
+            r = q % TH;
+            c = side ? TW - 1 : 0;
+            on = (side ? right : left) && ((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u);
+        }
+        if (on) {
             const int32_t comp = t.late.RT[node_at(t, r / G::RB, c)];
             atomicOr(&t.late.RFB[comp >> 5], 1u << (comp & 31));
         }
@@ -997,9 +996,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     for (int r = tid; r < TH; r += NT)
         if (y0 + r < im.H)
             im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.late.rowcnt[r];
-    uint16_t *grt = im.rt + (int64_t)ti * G::RCAP;
-    for (int k = tid; k < n_runs; k += NT)
-        grt[k] = t.late.RT[k];
+    // node -> component, two entries per store (an odd count writes one
+    // unused entry past the end, inside the tile's capacity)
+    uint32_t *grt2 = reinterpret_cast<uint32_t *>(im.rt + (int64_t)ti * G::RCAP);
+    const uint32_t *RT2 = reinterpret_cast<const uint32_t *>(t.late.RT);
+    for (int k = tid; 2 * k < n_runs; k += NT)
+        grt2[k] = RT2[k];
     int32_t *gck = im.cf + (int64_t)ti * G::RCAP;
     for (int c = tid; c < n_comp; c += NT)
         gck[c] = t.P[c];
