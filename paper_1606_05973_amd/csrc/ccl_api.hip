@@ -288,7 +288,8 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     pm.mark();
     if (edges > 0)
-        hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((edges + kThreads - 1) / kThreads)), blk, 0, s, b);
+        hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((merge_split(BH) * edges + kThreads - 1) / kThreads)),
+                           blk, 0, s, b);
     pm.mark();
     hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), dim3((uint32_t)((tiles + kWaves - 1) / kWaves)), blk, 0, s, b,
                        (int32_t)tiles);

@@ -1092,12 +1092,20 @@ __device__ __forceinline__ void line_bytes(const Img &im, bool horiz, int fixed,
     }
 }
 
+constexpr int merge_split(int bh) { return bh == 2 ? 1 : 2; }
+
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
     constexpr int TH = G::TH;
-    const int32_t item = blockIdx.x * kThreads + threadIdx.x;
+    // threads per 32-pixel segment: row-pair runs keep one (their large
+    // components make the split halves repeat each other's unions); single
+    // rows and gray levels split the segment's contacts over two threads,
+    // which halves the longest chains of dependent union steps
+    constexpr int MS = merge_split(BH);
+    const int32_t item2 = blockIdx.x * kThreads + threadIdx.x;
+    const int32_t item = MS == 2 ? item2 >> 1 : item2;
     const Img &im = find_img(b, item, kEdge);
     int32_t e = item - im.edge0;
     const int32_t nxs = (im.W + 31) >> 5, nys = (im.H + 31) >> 5;
@@ -1170,6 +1178,11 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
         // position outside the image reads 0, which no object byte equals)
         cm1 = (uint64_t)v | (conn8 ? ((uint64_t)(d1 & (from > 0 ? 0xFFFFFFFFu : 0xFFFFFFFEu)) << 32) : 0ull);
         cm2 = conn8 ? d2 : 0u;
+    }
+    if (MS == 2) {
+        const uint32_t hm = (item2 & 1) ? 0xFFFF0000u : 0x0000FFFFu;
+        cm1 &= (uint64_t)hm | ((uint64_t)hm << 32);
+        cm2 &= hm;
     }
     constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
     uint64_t *P = im.uf;
