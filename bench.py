@@ -46,22 +46,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload_key: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
+def load_counters(kernel: str, workload_key: str) -> dict:
+    """A kernel's figures from committed rocprofv3 counter runs (HBM bytes per
+    launch, VALU busy and lane use), if they were taken on the current kernel
+    sources; else an empty dict."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         data = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return {}
     if data.get("kernel_source_sha") != kernel_source_hash():
-        return None
-    ent = data.get("workloads", {}).get(workload_key, {}).get(kernel)
-    if not ent:
-        return None
-    return ent.get("hbm_bytes_per_launch")
+        return {}
+    return data.get("workloads", {}).get(workload_key, {}).get(kernel) or {}
 
 
 def log(msg):
@@ -307,7 +305,8 @@ def main():
                     "gray": f"gray{args.sigma}_level{level}" + (f"_bins{args.gray_bins}" if gray else "")}[args.content] + \
         f"_{S}x{S}_conn{args.conn}_tile{th}x{tw}" + (f"_pitch{stride}" if stride != S else "") + \
         ("_scanrow" if args.scan == "row" else "")
-    traffic = load_traffic(dom, workload_key)
+    counters = load_counters(dom, workload_key)
+    traffic = counters.get("hbm_bytes_per_launch")
 
     record = {
         "metric": METRIC,
@@ -338,6 +337,12 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "kernel_ms": round(dom_ms, 4),
+            # a kernel limited by VALU issue rather than HBM (the tile scan on
+            # dense noise) shows it here: the share of cycles in which a CU
+            # issued a VALU instruction, and the share of active lanes in
+            # those instructions (rocprofv3 SQ counters; null when absent)
+            "valu_busy": counters.get("valu_busy"),
+            "lane_use": counters.get("lane_use"),
         },
         "path_roofline_frac": round(BYTES_PER_PX * px / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
