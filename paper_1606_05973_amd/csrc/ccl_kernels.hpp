@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             const uint32_t up = t.M[ru * NW + w];
             const uint32_t uL = w ? t.M[ru * NW + w - 1] : 0u;
             const uint32_t o = m & up;
-            const uint32_t u1 = o & ~((o << 1) | ((mL & uL) >> 31));
+            uint32_t u1 = o & ~((o << 1) | ((mL & uL) >> 31));
             uint32_t u2 = 0u, u3 = 0u;
             if (conn8) {
                 const uint32_t mR = (w < NW - 1) ? t.M[rm * NW + w + 1] : 0u;
@@ -698,6 +698,22 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             const uint32_t C = u1 | u2 | u3;
             const uint32_t F = ((B & ~C) + t.S[u]) & C;
             const uint32_t d3 = F & u3, d1 = F & ~u3 & u1, d2 = F & ~u3 & ~u1 & u2;
+            if (G::RB == 2) {
+                // Row pairs: two contacts in one run of A (both block rows
+                // foreground) join the same two block runs (the partners,
+                // one column aside at most, are foreground next to that
+                // run), so only the first contact of each A run in the word
+                // is kept; where a U3 and a U2 share that column, the U2
+                // repeats it.  The direct link is the first contact of its
+                // block run, so it is always a kept one.
+                const uint32_t A = B & block_mask<NSR, TW, BH>(t.M, R - 1, w);
+                const uint32_t CA = C & A;
+                const uint32_t first = ((A & ~CA) + (A & ~(A << 1))) & CA;
+                const uint32_t keep = ~(CA & ~first);
+                u1 &= keep;
+                u3 &= keep;
+                u2 &= keep & ~(first & u3);
+            }
             // this thread's share of the word's contact positions
             constexpr int PART = 32 / LPU;
             const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
