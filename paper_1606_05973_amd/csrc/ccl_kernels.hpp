@@ -199,19 +199,17 @@ __device__ __forceinline__ V acas(P *p, V expect, V v) {
 // (key of parent << 32 | parent id), so comparing packed parents compares
 // their keys and every set's root is the node with the smallest key.)
 
-// Find with full path compression, used only after all unions are done (the
-// root is fixed and the only value ever stored is the root's).
+// Find after all unions are done: the roots are fixed, so each node stores
+// its own root and nothing else (a concurrent walk reads either the old
+// parent, an ancestor, or the root).  Every node has its own thread, so the
+// path's other nodes are set by theirs; compressing them too measured slower.
 template <int S>
-__device__ int32_t find_compress(int32_t *P, int32_t x) {
+__device__ int32_t find_root_store(int32_t *P, int32_t x) {
     int32_t r = x, p;
     while ((p = aload<S>(P + r)) != r)
         r = p;
-    int32_t y = x;
-    while (y != r) {
-        int32_t nx = aload<S>(P + y);
-        astore<S>(P + y, r);
-        y = nx;
-    }
+    if (r != x)
+        astore<S>(P + x, r);
     return r;
 }
 
@@ -861,7 +859,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const int k = k0 + tid;
         bool root = false;
         if (k < n_runs)
-            root = find_compress<WG>(t.P, k) == k;
+            root = find_root_store<WG>(t.P, k) == k;
         const uint64_t bal = __ballot(root);
         const int wd = (k0 + wave * 64) >> 5;
         if (lane == 0 && wd < G::RW)
