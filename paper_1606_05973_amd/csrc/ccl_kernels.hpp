@@ -482,6 +482,29 @@ __device__ int32_t number_runs(RunLds<NSR, TW, BH> &t, const uint32_t *E = nullp
 // ------------------------------------------------------------------------
 // K1: tile scan.
 // ------------------------------------------------------------------------
+// Node ordinals around the (block row, word) unit u of a contact row, from
+// its run starts and bases (and those of the three units above it): the node
+// of block row R whose run covers column c of the word, and the node of block
+// row R - 1 covering column pc (-1 .. 32: a partner one column past either
+// end of the word lies in the neighbouring word).  Plain values throughout:
+// a select between the addresses of struct members would leave them in
+// private memory.
+#define CCL_UNIT_RUNS(t, u)                                        \
+    const int w_ = (u) % NW, uu_ = (u) - NW;                       \
+    const uint32_t sR = t.S[u], sU = t.S[uu_];                     \
+    const int32_t bR = t.base[u] - 1, bU = t.base[uu_] - 1;        \
+    const uint32_t sUL = w_ ? t.S[uu_ - 1] : 0u;                   \
+    const int32_t bUL = w_ ? t.base[uu_ - 1] - 1 : 0;              \
+    const uint32_t sUR = (w_ < NW - 1) ? t.S[uu_ + 1] : 0u;        \
+    const int32_t bUR = (w_ < NW - 1) ? t.base[uu_ + 1] - 1 : 0
+__device__ __forceinline__ int32_t run_node(uint32_t s, int32_t b, int c) { return b + __popc(s & mask_le(c)); }
+__device__ __forceinline__ int32_t upper_node(int pc, uint32_t sUL, uint32_t sU, uint32_t sUR, int32_t bUL,
+                                              int32_t bU, int32_t bUR) {
+    const uint32_t sp = pc < 0 ? sUL : (pc > 31 ? sUR : sU);
+    const int32_t bp = pc < 0 ? bUL : (pc > 31 ? bUR : bU);
+    return bp + __popc(sp & mask_le(pc & 31));
+}
+
 template <int NSR, int TW, int BH>
 struct ScanLate {
     using G = Geo<NSR, TW, BH>;
@@ -638,10 +661,16 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     // (compacted by a block scan), then the pairs are dealt out evenly to
     // the threads, which apply Rem's union with splicing to them.  A tile
     // with more contacts than the list holds is done in several rounds.
-    uint64_t cm1[UPT2];  // U1 positions (low half; partner at c) and U3 (high half; partner at c-1)
-    uint32_t cm2[UPT2];  // U2 positions (partner at c+1)
-    uint64_t dm1[UPT2];  // first contact of a run starting in the word: direct link, same layout
-    uint32_t dm2[UPT2];
+    // Contacts to list, one per column: the partner is at c + d with d = 0
+    // (U1), -1 where the column's bit is set in cn (U3), +1 where it is set
+    // in cp (U2).  A column with more than one contact (U3 and U2 at a lone
+    // lower pixel; with gray levels also U1 and a diagonal) lists the others
+    // from cx: low half d = -1, high half d = +1.  The direct links (the
+    // first contact of a run starting in the word) use the same one-per-
+    // column form in df, dn, dp.
+    uint32_t cl[UPT2], cn[UPT2], cp[UPT2];
+    uint64_t cx[UPT2];
+    uint32_t df[UPT2], dn[UPT2], dp[UPT2];
     int32_t coff[UPT2];
     int32_t n_pairs = 0;
 #pragma unroll
@@ -649,10 +678,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const int v = tid + k * NT;
         const int u = v % G::NU, h = v / G::NU;
         const int R = u / NW, w = u % NW;
-        cm1[k] = 0;
-        cm2[k] = 0u;
-        dm1[k] = 0;
-        dm2[k] = 0u;
+        cl[k] = cn[k] = cp[k] = 0u;
+        cx[k] = 0;
+        df[k] = dn[k] = dp[k] = 0u;
         if (GRAY && h < LPU && R > 0) {
             // gray levels (one row per block row): U1 at the first column of
             // each stretch where the pixel above has the same value and both
@@ -669,8 +697,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             }
             constexpr int PART = 32 / LPU;
             const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
-            cm1[k] = (uint64_t)(u1 & mine) | ((uint64_t)(u3 & mine) << 32);
-            cm2[k] = u2 & mine;
+            cl[k] = (u1 | u2 | u3) & mine;
+            cn[k] = u3 & ~u1 & mine;
+            cp[k] = u2 & ~u1 & ~u3 & mine;
+            cx[k] = (uint64_t)(u3 & u1 & mine) | ((uint64_t)(u2 & (u1 | u3) & mine) << 32);
         } else if (!GRAY && h < LPU && R > 0) {
             const int rm = R * G::RB, ru = R * G::RB - 1;
             const uint32_t m = t.M[rm * NW + w];
@@ -715,13 +745,19 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             // this thread's share of the word's contact positions
             constexpr int PART = 32 / LPU;
             const uint32_t mine = (PART == 32 ? 0xFFFFFFFFu : ((1u << PART) - 1u)) << (h * PART);
-            cm1[k] = (uint64_t)(u1 & ~d1 & mine) | ((uint64_t)(u3 & ~d3 & mine) << 32);
-            cm2[k] = u2 & ~d2 & mine;
-            dm1[k] = (uint64_t)(d1 & mine) | ((uint64_t)(d3 & mine) << 32);
-            dm2[k] = d2 & mine;
+            // (row runs never give U1 and U3 at one column: the pixel above
+            // decides which)
+            const uint32_t l1 = u1 & ~d1, l3 = u3 & ~d3, l2 = u2 & ~d2;
+            cl[k] = (l1 | l2 | l3) & mine;
+            cn[k] = l3 & mine;
+            cp[k] = l2 & ~l3 & mine;
+            cx[k] = (uint64_t)(l2 & l3 & mine) << 32;
+            df[k] = F & mine;
+            dn[k] = d3 & mine;
+            dp[k] = d2 & mine;
         }
         int32_t tot;
-        coff[k] = n_pairs + block_exclusive_scan<NT>(__popcll(cm1[k]) + __popc(cm2[k]), &tot);
+        coff[k] = n_pairs + block_exclusive_scan<NT>(__popc(cl[k]) + __popcll(cx[k]), &tot);
         n_pairs += tot;
     }
     // direct links (the scan's copy step: a pixel whose first neighbour is
@@ -732,80 +768,45 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     // further contacts are merged as before.
 #pragma unroll
     for (int k = 0; k < UPT2; k++) {
-        uint64_t a = dm1[k];
-        uint32_t c2 = dm2[k];
-        if (!a && !c2)
+        uint32_t l = df[k];
+        if (!l)
             continue;
         const int u = (tid + k * NT) % G::NU;
-        const int w = u % NW;
-        const uint32_t sR = t.S[u];
-        const int32_t bR = t.base[u] - 1;
-        const int uu = u - NW;
-        const uint32_t sU = t.S[uu];
-        const int32_t bU = t.base[uu] - 1;
-        const uint32_t sUL = w ? t.S[uu - 1] : 0u;
-        const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
-        const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
-        const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
-        while (a || c2) {
-            int c, d;
-            if (a) {
-                const int bit = __ffsll((unsigned long long)a) - 1;
-                a &= a - 1;
-                c = bit & 31;
-                d = (bit >> 5) ? -1 : 0;
-            } else {
-                c = __ffs(c2) - 1;
-                c2 &= c2 - 1u;
-                d = 1;
-            }
-            const int32_t x = bR + __popc(sR & mask_le(c));
-            const int pc = c + d;
-            const uint32_t sp = pc < 0 ? sUL : (pc > 31 ? sUR : sU);
-            const int32_t bp = pc < 0 ? bUL : (pc > 31 ? bUR : bU);
-            t.P[x] = bp + __popc(sp & mask_le(pc & 31));
-        }
+        CCL_UNIT_RUNS(t, u);
+        do {
+            const int c = __ffs(l) - 1;
+            l &= l - 1u;
+            const int d = (int)((dp[k] >> c) & 1u) - (int)((dn[k] >> c) & 1u);
+            t.P[run_node(sR, bR, c)] = upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR);
+        } while (l);
     }
     for (int r0 = 0; r0 < n_pairs; r0 += ScanLds<NSR, TW, BH>::PRCAP) {
         const int r1 = r0 + ScanLds<NSR, TW, BH>::PRCAP;
 #pragma unroll
         for (int k = 0; k < UPT2; k++) {
             int32_t idx = coff[k];
-            uint64_t a = cm1[k];
-            uint32_t c2 = cm2[k];
-            if ((!a && !c2) || idx >= r1)
+            uint32_t l = cl[k];
+            uint64_t x2 = cx[k];
+            if ((!l && !x2) || idx >= r1)
                 continue;
             const int u = (tid + k * NT) % G::NU;
-            const int w = u % NW;
-            const uint32_t sR = t.S[u];
-            const int32_t bR = t.base[u] - 1;
-            const int uu = u - NW;
-            const uint32_t sU = t.S[uu];
-            const int32_t bU = t.base[uu] - 1;
-            const uint32_t sUL = w ? t.S[uu - 1] : 0u;
-            const int32_t bUL = w ? t.base[uu - 1] - 1 : 0;
-            const uint32_t sUR = (w < NW - 1) ? t.S[uu + 1] : 0u;
-            const int32_t bUR = (w < NW - 1) ? t.base[uu + 1] - 1 : 0;
-            while ((a || c2) && idx < r1) {
-                int c, d;
-                if (a) {
-                    const int bit = __ffsll((unsigned long long)a) - 1;
-                    a &= a - 1;
-                    c = bit & 31;
-                    d = (bit >> 5) ? -1 : 0;
-                } else {
-                    c = __ffs(c2) - 1;
-                    c2 &= c2 - 1u;
-                    d = 1;
-                }
-                if (idx >= r0) {
-                    const int32_t x = bR + __popc(sR & mask_le(c));
-                    const int pc = c + d;
-                    const uint32_t sp = pc < 0 ? sUL : (pc > 31 ? sUR : sU);
-                    const int32_t bp = pc < 0 ? bUL : (pc > 31 ? bUR : bU);
-                    const int32_t y = bp + __popc(sp & mask_le(pc & 31));
-                    t.PR[idx - r0] = (uint32_t)x | ((uint32_t)y << 16);
-                }
+            CCL_UNIT_RUNS(t, u);
+            while (l && idx < r1) {
+                const int c = __ffs(l) - 1;
+                l &= l - 1u;
+                const int d = (int)((cp[k] >> c) & 1u) - (int)((cn[k] >> c) & 1u);
+                if (idx >= r0)
+                    t.PR[idx - r0] = (uint32_t)run_node(sR, bR, c) |
+                                     ((uint32_t)upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR) << 16);
+                idx++;
+            }
+            while (x2 && idx < r1) {
+                const int bit = __ffsll((unsigned long long)x2) - 1;
+                x2 &= x2 - 1;
+                const int c = bit & 31, d = (bit >> 5) ? 1 : -1;
+                if (idx >= r0)
+                    t.PR[idx - r0] = (uint32_t)run_node(sR, bR, c) |
+                                     ((uint32_t)upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR) << 16);
                 idx++;
             }
         }
