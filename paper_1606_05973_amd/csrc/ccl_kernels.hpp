@@ -199,16 +199,19 @@ __device__ __forceinline__ V acas(P *p, V expect, V v) {
 // (key of parent << 32 | parent id), so comparing packed parents compares
 // their keys and every set's root is the node with the smallest key.)
 
-// Find after all unions are done: the roots are fixed, so each node stores
-// its own root and nothing else (a concurrent walk reads either the old
-// parent, an ancestor, or the root).  Every node has its own thread, so the
-// path's other nodes are set by theirs; compressing them too measured slower.
+// Find after all unions are done, on a parent array of byte offsets (4 x
+// node): the roots are fixed, so each node stores its own root and nothing
+// else (a concurrent walk reads either the old parent, an ancestor, or the
+// root).  Every node has its own thread, so the path's other nodes are set
+// by theirs; compressing them too measured slower.  Returns the root's
+// byte offset.
 template <int S>
 __device__ int32_t find_root_store(int32_t *P, int32_t x) {
-    int32_t r = x, p;
-    while ((p = aload<S>(P + r)) != r)
+    char *base = reinterpret_cast<char *>(P);
+    int32_t r = 4 * x, p;
+    while ((p = aload<S>(reinterpret_cast<int32_t *>(base + r))) != r)
         r = p;
-    if (r != x)
+    if (r != 4 * x)
         astore<S>(P + x, r);
     return r;
 }
@@ -648,9 +651,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             }
         }
     }
+    // The parent array holds byte offsets (4 x node) until the flatten, so
+    // that a union step addresses a parent without a shift.
     for (int k = tid; k < n_runs; k += NT)
-        t.P[k] = k;
+        t.P[k] = 4 * k;
     __syncthreads();
+    auto at = [&](int32_t off) { return reinterpret_cast<int32_t *>(reinterpret_cast<char *>(t.P) + off); };
 
     // 3. unite touching nodes of block rows R-1 and R.  The contact rows are
     // the last row of R-1 (u) and the first row of R (m).  Each touching pair
@@ -777,7 +783,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             const int c = __ffs(l) - 1;
             l &= l - 1u;
             const int d = (int)((dp[k] >> c) & 1u) - (int)((dn[k] >> c) & 1u);
-            t.P[run_node(sR, bR, c)] = upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR);
+            t.P[run_node(sR, bR, c)] = 4 * upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR);
         } while (l);
     }
     for (int r0 = 0; r0 < n_pairs; r0 += ScanLds<NSR, TW, BH>::PRCAP) {
@@ -815,21 +821,21 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         // and takes its next pair as soon as the current union ends.
         const int np = min(n_pairs - r0, ScanLds<NSR, TW, BH>::PRCAP);
         int q = tid;
-        int32_t rx = 0, ry = 0;
+        int32_t rx = 0, ry = 0;  // byte offsets of the two nodes
         if (q < np) {
             const uint32_t pr = t.PR[q];
-            rx = (int32_t)(pr & 0xFFFFu);
-            ry = (int32_t)(pr >> 16);
+            rx = (int32_t)((pr & 0xFFFFu) << 2);
+            ry = (int32_t)((pr >> 16) << 2);
         }
         // Branch-free step: when both parents are equal the compare-and-swap
         // puts the value onto itself and changes nothing.
         while (q < np) {
-            const int32_t px = aload<WG>(t.P + rx);
-            const int32_t py = aload<WG>(t.P + ry);
+            const int32_t px = aload<WG>(at(rx));
+            const int32_t py = aload<WG>(at(ry));
             const bool xs = px > py;
             const int32_t n = xs ? rx : ry;
             const int32_t pn = xs ? px : py;
-            const int32_t seen = acas<WG>(t.P + n, pn, xs ? py : px);
+            const int32_t seen = acas<WG>(at(n), pn, xs ? py : px);
             const bool ok = seen == pn;
             const bool next = px == py || (ok && pn == n);
             rx = ok && xs ? pn : rx;
@@ -837,8 +843,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             if (next) {
                 q += NT;
                 const uint32_t pr = t.PR[min(q, np - 1)];
-                rx = (int32_t)(pr & 0xFFFFu);
-                ry = (int32_t)(pr >> 16);
+                rx = (int32_t)((pr & 0xFFFFu) << 2);
+                ry = (int32_t)((pr >> 16) << 2);
             }
         }
         __syncthreads();
@@ -860,7 +866,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const int k = k0 + tid;
         bool root = false;
         if (k < n_runs)
-            root = find_root_store<WG>(t.P, k) == k;
+            root = find_root_store<WG>(t.P, k) == 4 * k;
         const uint64_t bal = __ballot(root);
         const int wd = (k0 + wave * 64) >> 5;
         if (lane == 0 && wd < G::RW)
@@ -875,7 +881,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const int k = k0 + tid;
         bool same_row = false;
         if (k < n_runs) {
-            const int32_t root = t.P[k];
+            const int32_t root = t.P[k] >> 2;
             t.late.RT[k] = (uint16_t)rank_of(t.late.RFB, t.late.RFP, root);
             same_row = (t.SP[k] / TW) == (t.SP[root] / TW);
         }
