@@ -223,6 +223,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t mask_le(int b) { return 0xFFFFFFFFu >> (31 - b); }  // bits 0..b
+// set bits of s at positions 0..b (0 <= b <= 31): shifted to the top, one
+// instruction fewer than masking
+__device__ __forceinline__ int popc_le(uint32_t s, int b) { return __popc(s << (31 - b)); }
 __device__ __forceinline__ uint32_t mask_lt(int b) { return (1u << b) - 1u; }          // bits 0..b-1
 __device__ __forceinline__ uint32_t mask_ge(int b) { return 0xFFFFFFFFu << b; }        // bits b..31
 
@@ -442,7 +445,7 @@ template <int NSR, int TW, int BH>
 __device__ __forceinline__ int32_t node_at(const RunLds<NSR, TW, BH> &t, int R, int c) {
     constexpr int NW = Geo<NSR, TW, BH>::NW;
     const int u = R * NW + (c >> 5);
-    return t.base[u] - 1 + __popc(t.S[u] & mask_le(c & 31));
+    return t.base[u] - 1 + popc_le(t.S[u], c & 31);
 }
 
 // Fills S and base from M; returns the number of nodes (same on all threads).
@@ -486,26 +489,23 @@ __device__ int32_t number_runs(RunLds<NSR, TW, BH> &t, const uint32_t *E = nullp
 // K1: tile scan.
 // ------------------------------------------------------------------------
 // Node ordinals around the (block row, word) unit u of a contact row, from
-// its run starts and bases (and those of the three units above it): the node
-// of block row R whose run covers column c of the word, and the node of block
-// row R - 1 covering column pc (-1 .. 32: a partner one column past either
-// end of the word lies in the neighbouring word).  Plain values throughout:
-// a select between the addresses of struct members would leave them in
-// private memory.
-#define CCL_UNIT_RUNS(t, u)                                        \
-    const int w_ = (u) % NW, uu_ = (u) - NW;                       \
-    const uint32_t sR = t.S[u], sU = t.S[uu_];                     \
-    const int32_t bR = t.base[u] - 1, bU = t.base[uu_] - 1;        \
-    const uint32_t sUL = w_ ? t.S[uu_ - 1] : 0u;                   \
-    const int32_t bUL = w_ ? t.base[uu_ - 1] - 1 : 0;              \
-    const uint32_t sUR = (w_ < NW - 1) ? t.S[uu_ + 1] : 0u;        \
-    const int32_t bUR = (w_ < NW - 1) ? t.base[uu_ + 1] - 1 : 0
-__device__ __forceinline__ int32_t run_node(uint32_t s, int32_t b, int c) { return b + __popc(s & mask_le(c)); }
-__device__ __forceinline__ int32_t upper_node(int pc, uint32_t sUL, uint32_t sU, uint32_t sUR, int32_t bUL,
-                                              int32_t bU, int32_t bUR) {
-    const uint32_t sp = pc < 0 ? sUL : (pc > 31 ? sUR : sU);
-    const int32_t bp = pc < 0 ? bUL : (pc > 31 ? bUR : bU);
-    return bp + __popc(sp & mask_le(pc & 31));
+// run starts and bases: the node of block row R whose run covers column c of
+// the word, and the node of block row R - 1 covering column pc (-1 .. 32: a
+// partner one column past either end of the word).  The upper row's starts
+// sit in a 64-bit window, shifted up one bit, with bit 0 of the next word's
+// starts above them: the nodes up to pc are the window's bits 0 .. pc + 1
+// (bit 0, column -1, is never set: a partner left of the word is the last
+// node before the word's own, bU).  Plain values throughout: a select between
+// the addresses of struct members would leave them in private memory.
+#define CCL_UNIT_RUNS(t, u)                                                            \
+    const int w_ = (u) % NW, uu_ = (u) - NW;                                           \
+    const uint32_t sR = t.S[u];                                                        \
+    const int32_t bR = t.base[u] - 1, bU = t.base[uu_] - 1;                            \
+    const uint64_t wU = ((uint64_t)((w_ < NW - 1) ? (t.S[uu_ + 1] & 1u) : 0u) << 33) | \
+                        ((uint64_t)t.S[uu_] << 1)
+__device__ __forceinline__ int32_t run_node(uint32_t s, int32_t b, int c) { return b + popc_le(s, c); }
+__device__ __forceinline__ int32_t upper_node(int pc, uint64_t wU, int32_t bU) {
+    return bU + __popcll(wU << (62 - pc));
 }
 
 template <int NSR, int TW, int BH>
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             const int c = __ffs(l) - 1;
             l &= l - 1u;
             const int d = (int)((dp[k] >> c) & 1u) - (int)((dn[k] >> c) & 1u);
-            t.P[run_node(sR, bR, c)] = 4 * upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR);
+            t.P[run_node(sR, bR, c)] = 4 * upper_node(c + d, wU, bU);
         } while (l);
     }
     for (int r0 = 0; r0 < n_pairs; r0 += ScanLds<NSR, TW, BH>::PRCAP) {
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                 const int d = (int)((cp[k] >> c) & 1u) - (int)((cn[k] >> c) & 1u);
                 if (idx >= r0)
                     t.PR[idx - r0] = (uint32_t)run_node(sR, bR, c) |
-                                     ((uint32_t)upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR) << 16);
+                                     ((uint32_t)upper_node(c + d, wU, bU) << 16);
                 idx++;
             }
             while (x2 && idx < r1) {
@@ -812,7 +812,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                 const int c = bit & 31, d = (bit >> 5) ? 1 : -1;
                 if (idx >= r0)
                     t.PR[idx - r0] = (uint32_t)run_node(sR, bR, c) |
-                                     ((uint32_t)upper_node(c + d, sUL, sU, sUR, bUL, bU, bUR) << 16);
+                                     ((uint32_t)upper_node(c + d, wU, bU) << 16);
                 idx++;
             }
         }
