@@ -396,24 +396,6 @@ __device__ __forceinline__ int32_t wave_popcount_prefix(const uint32_t *bits, in
     return carry;
 }
 
-// Exclusive popcount prefix of n bitmask words (n may exceed NT).  pref is
-// written after the last barrier: a caller that reads entries written by
-// other waves needs a barrier first.
-template <int NT>
-__device__ __forceinline__ int32_t popcount_prefix(const uint32_t *bits, int32_t *pref, int n) {
-    int32_t carry = 0;
-    for (int base = 0; base < n; base += NT) {
-        int i = base + threadIdx.x;
-        int32_t v = i < n ? __popc(bits[i]) : 0;
-        int32_t tot;
-        int32_t ex = block_exclusive_scan<NT>(v, &tot);
-        if (i < n)
-            pref[i] = carry + ex;
-        carry += tot;
-    }
-    return carry;
-}
-
 __device__ __forceinline__ int32_t rank_of(const uint32_t *bits, const int32_t *pref, int32_t k) {
     return pref[k >> 5] + __popc(bits[k >> 5] & mask_lt(k & 31));
 }
@@ -517,6 +499,7 @@ struct ScanLate {
     int32_t RFP[G::RW];
     uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
     int32_t rowcnt[G::TH];
+    int32_t ncomp;          // local component count, for every wave
 };
 
 template <int NSR, int TW, int BH>
@@ -875,8 +858,14 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             t.late.RFB[wd + 1] = (uint32_t)(bal >> 32);
     }
     __syncthreads();
-    const int32_t n_comp = popcount_prefix<NT>(t.late.RFB, t.late.RFP, (n_runs + 31) >> 5);
+    // (prefixes over at most RW words: one wave does them, the others skip)
+    if (wave == 0) {
+        const int32_t tot = wave_popcount_prefix(t.late.RFB, t.late.RFP, (n_runs + 31) >> 5, lane);
+        if (lane == 0)
+            t.late.ncomp = tot;
+    }
     __syncthreads();
+    const int32_t n_comp = t.late.ncomp;
     for (int k0 = 0; k0 < n_runs; k0 += NT) {
         const int k = k0 + tid;
         bool same_row = false;
@@ -965,7 +954,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
     }
     __syncthreads();
-    const int32_t n_bound = popcount_prefix<NT>(t.late.RFB, t.late.RFP, (n_comp + 31) >> 5);
+    int32_t n_bound = 0;  // known to the first wave, which exports it
+    if (wave == 0)
+        n_bound = wave_popcount_prefix(t.late.RFB, t.late.RFP, (n_comp + 31) >> 5, lane);
     for (int c = tid; c < n_comp; c += NT) {
         if (!((t.late.RFB[c >> 5] >> (c & 31)) & 1u)) {
             const int32_t key = t.P[c];
