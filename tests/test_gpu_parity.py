@@ -262,6 +262,40 @@ def test_threshold_full_size_im2bw(ccl):
 
 
 # ------------------------------------------------------ scan strategy (rows)
+def _diag_contact_image(H, W, s):
+    """Period of four rows: lone pixels at every fourth column, a full row, an
+    empty row, pixels at every other column.  Each lone pixel has foreground
+    above-left and above-right but not above, so one column holds two diagonal
+    contacts with different upper runs; the full row below joins the lone
+    pixels into one long run, so neither contact is its run's first."""
+    r = np.arange(H)[:, None] % 4
+    c = (np.arange(W)[None, :] - s) % 4
+    img = ((r == 0) & (c == 1)) | (r == 1) | ((r == 3) & (c % 2 == 0))
+    return img.astype(np.uint8)
+
+
+@pytest.mark.parametrize("scan", ["pair", "row"])
+def test_diagonal_contacts_sharing_a_column(ccl, scan):
+    """Two diagonal contacts at one column, at every bit position of a mask
+    word (four shifts; partners one column into the neighbouring word at bit 0
+    and bit 31), flipped both ways, on ragged widths."""
+    sc = ccl.SCAN_PAIR if scan == "pair" else ccl.SCAN_ROW
+    for (H, W) in [(133, 333), (70, 1000)]:
+        for s in range(4):
+            base = _diag_contact_image(H, W, s)
+            for flip in (None, 0, 1, (0, 1)):
+                a = base if flip is None else np.ascontiguousarray(np.flip(base, flip))
+                img = torch.from_numpy(a).to(DEV)
+                for conn in (8, 4):
+                    say(f"case diagonal pattern scan={scan} shape={(H, W)} shift={s} flip={flip} conn={conn}")
+                    k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+                    got = ccl.label(img, conn, num_components=k, scan=sc)
+                    torch.cuda.synchronize()
+                    ref, kref = oracle.cclremsp(a, conn)
+                    assert np.array_equal(got.cpu().numpy(), ref), (H, W, s, flip, conn)
+                    assert int(k.item()) == kref
+
+
 @pytest.mark.parametrize("tile", [0, 3, 6])
 def test_one_row_scan_8conn(ccl, tile):
     """The one-row tile scan (runs of single rows, diagonal contacts as
