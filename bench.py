@@ -33,8 +33,9 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E peak, GB/s
 BYTES_PER_PX = 5            # compulsory: 1 B image read + 4 B int32 label write
 # algorithmic bytes per pixel of each phase's launch: the tile scan reads the
 # image (1 B/px); the labeling pass writes the labels (4 B/px) and reads the
-# image information once more, as a 1-bit mask in place of the bytes (1 B/px)
-PHASE_BYTES_PER_PX = {"tile_scan": 1.0, "labeling_pass": 5.0}
+# image information once more, as a 1-bit mask in place of the bytes
+# (1/8 B/px)
+PHASE_BYTES_PER_PX = {"tile_scan": 1.0, "labeling_pass": 4.125}
 METRIC = "Gpixel/s and % of HBM roofline, 8-conn, bit-exact; batched/served vs single"
 
 
@@ -60,6 +61,18 @@ def load_counters(kernel: str, workload_key: str) -> dict:
     if data.get("kernel_source_sha") != kernel_source_hash():
         return {}
     return data.get("workloads", {}).get(workload_key, {}).get(kernel) or {}
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def log(msg):
@@ -130,13 +143,20 @@ def bench_batched(torch, n, conn, reps, verify):
 
 
 def bench_served(torch, rates, nreq, verify):
-    """Poisson request streams through the continuous-batching server."""
+    """Request streams through the continuous-batching server: Poisson
+    arrivals at each rate, then a closed-loop run ("max": every request
+    submitted at once) that measures the served capacity."""
     import numpy as np
 
     from paper_1606_05973_amd import ccl, inputs, serve
     dev = torch.device("cuda:0")
     _, specs = inputs.serve_specs(1, 1.0, seed=0, pool=256)
     pool = [inputs.make(sp, device=dev) for sp in specs]
+    # one label buffer per (pool image, connectivity): requests for the same
+    # pair write the same labels, and submission stays cheap enough on the
+    # host to offer the higher rates
+    outs = {(i, c): torch.empty(tuple(im.shape), dtype=torch.int32, device=dev)
+            for i, im in enumerate(pool) for c in (4, 8)}
     torch.cuda.synchronize()
     log("served: pool made")
     res = {"pool_images": len(pool), "requests_per_rate": nreq, "rates": {}}
@@ -145,29 +165,33 @@ def bench_served(torch, rates, nreq, verify):
     srv = serve.Server(hbm_budget=16 << 30, n_streams=3, max_batch=64, device=dev)
     warm, _ = inputs.serve_specs(64, 1000.0, seed=1, pool=256)
     for q in warm:
-        srv.submit(pool[q["img"]], q["conn"])
+        srv.submit(pool[q["img"]], q["conn"], out=outs[(q["img"], q["conn"])], ready=False)
     srv.drain()
     for rate in rates:
-        reqs, _ = inputs.serve_specs(nreq, float(rate), seed=0, pool=256)
+        closed = rate == "max"
+        reqs, _ = inputs.serve_specs(nreq, 1000.0 if closed else float(rate), seed=0, pool=256)
         before = srv.stats()
-        kept = []
+        kept, late = [], 0.0
         t0 = time.perf_counter()
         for n, q in enumerate(reqs):
-            # sleep until the arrival time; requests already due go at once
-            wait = t0 + q["t"] - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
-            r = srv.submit(pool[q["img"]], q["conn"])
+            if not closed:
+                # sleep until the arrival time; requests already due go at once
+                wait = t0 + q["t"] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                else:
+                    late = max(late, -wait)
+            r = srv.submit(pool[q["img"]], q["conn"], out=outs[(q["img"], q["conn"])], ready=False)
             if n % 97 == 0:
                 kept.append(r)
+        t_sub = time.perf_counter()
         srv.drain()
         t1 = time.perf_counter()
         st = srv.stats(t0, t1)
-        lat = sorted(r.latency for r in kept)
         done = st["completed"] - before["completed"]
         # per-rate latency percentiles: over this rate's requests only
         rate_stats = srv.latency_stats(int(before["submitted"]) + 1, int(st["submitted"]))
-        offered = sum(pool[q["img"]].numel() for q in reqs) / reqs[-1]["t"] / 1e9
+        mpx = sum(pool[q["img"]].numel() for q in reqs) / 1e6
         ok = True
         for r in kept:
             alone = ccl.label(r.img, r.conn)
@@ -178,14 +202,23 @@ def bench_served(torch, rates, nreq, verify):
                 ok &= bool(np.array_equal(r.labels.cpu().numpy(), oracle.cclremsp(r.img.cpu().numpy(), r.conn)[0]))
         all_ok &= ok
         px = st["pixels_completed"] - before["pixels_completed"]
-        log(f"served rate {rate}: {done} done, p50 {rate_stats['p50_ms']:.2f} ms, p99 {rate_stats['p99_ms']:.2f} ms")
-        res["rates"][str(rate)] = {
-            "offered_gpx_per_s": round(offered, 2), "gpx_per_s": round(px / (t1 - t0) / 1e9, 2),
+        log(f"served rate {rate}: {done} done in {t1 - t0:.2f} s, p50 {rate_stats['p50_ms']:.2f} ms, "
+            f"p99 {rate_stats['p99_ms']:.2f} ms, {px / (t1 - t0) / 1e9:.1f} Gpx/s")
+        rec = {
+            "gpx_per_s": round(px / (t1 - t0) / 1e9, 2),
+            "req_per_s": round(done / (t1 - t0), 1),
             "p50_ms": round(rate_stats["p50_ms"], 3), "p99_ms": round(rate_stats["p99_ms"], 3),
-            "mean_ms": round(rate_stats["mean_ms"], 3), "completed": done,
+            "mean_ms": round(rate_stats["mean_ms"], 3), "completed": done, "mpx": round(mpx, 1),
             "batches": st["batches"] - before["batches"], "max_batches_in_flight": st["max_batches_in_flight"],
-            "alone_equals_mix_checked": len(kept), "sampled_p50_ms": round(lat[len(lat) // 2] * 1e3, 3),
+            "host_submit_s": round(t_sub - t0, 3),
+            "alone_equals_mix_checked": len(kept),
         }
+        if closed:
+            rec["offered"] = "all requests submitted at once (closed loop)"
+        else:
+            rec["offered_gpx_per_s"] = round(mpx / 1e3 / reqs[-1]["t"], 2)
+            rec["max_submit_lag_ms"] = round(late * 1e3, 3)
+        res["rates"][str(rate)] = rec
     srv.close()
     res["alone_equals_mix"] = all_ok
     return res
@@ -219,9 +252,10 @@ def main():
                     help="steps of the one-row vs two-row scan comparison (0 = skip)")
     ap.add_argument("--batch", type=int, default=256, help="images in the batched measurement (0 = skip)")
     ap.add_argument("--batch-reps", type=int, default=10)
-    ap.add_argument("--serve-rates", default="1000,5000,10000,20000",
-                    help="Poisson request rates (req/s) for the served measurement ('' = skip)")
-    ap.add_argument("--serve-requests", type=int, default=4000, help="requests per rate")
+    ap.add_argument("--serve-rates", default="1000,5000,10000,20000,50000,max",
+                    help="Poisson request rates (req/s) for the served measurement, 'max' = closed loop "
+                         "('' = skip)")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests per rate")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a plain copy kernel "
                          "of known size, used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -273,19 +307,23 @@ def main():
 
     ccl.profile(True)
     ccl.profile_read()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
+    # one event before every step and one after the last, all on the stream
+    # the library runs on (torch's current stream): per-step times without a
+    # host synchronisation inside the timed region
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
+    marks[0].record()
+    for i in range(args.steps):
         step(kdev)
-    end.record()
+        marks[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ccl.profile(False)
     phases, ncalls = ccl.profile_read()
-    ms_step = start.elapsed_time(end) / args.steps
+    step_ms = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
+    ms_step = statistics.median(step_ms)
+    ms_mean = marks[0].elapsed_time(marks[-1]) / args.steps
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         src = torch.ones(n, dtype=torch.uint8, device=dev)
@@ -316,6 +354,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_mean": round(ms_mean, 4),
+        "ms_per_step_min_max": [round(min(step_ms), 4), round(max(step_ms), 4)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -367,14 +407,17 @@ def main():
             times.append(time.perf_counter() - t)
         if args.cpu_runs > 0:
             med = statistics.median(times)
+            cpu = host_cpu_model()
             record["cpu_baseline"] = {
                 "value": round(px / med / 1e9, 4),
                 "unit": "Gpixel/s",
                 "cores": 1,
                 "kind": "oracle",
+                "cpu_model": cpu,
+                "host_threads": os.cpu_count(),
                 "sample": f"the full {S}x{S} image, single-threaded C "
                           f"{'gray-level two-pass labeling' if gray else 'CCLRemSP'}, median of {len(times)} runs "
-                          f"({med:.2f} s each)",
+                          f"({med:.2f} s each) on one core of {cpu}",
             }
         if not args.no_verify:
             record["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), ref)) and int(kdev.item()) == kref
@@ -403,7 +446,7 @@ def main():
                              for c in (args.conn, 12 - args.conn)]
         torch.cuda.empty_cache()
         ccl.release()
-    rates = [int(x) for x in args.serve_rates.split(",") if x.strip()]
+    rates = [x.strip() if x.strip() == "max" else int(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates and args.serve_requests > 0:
         log("served")
         record["served"] = bench_served(torch, rates, args.serve_requests, not args.no_verify)

@@ -41,7 +41,7 @@ typedef enum {
     CCL_ERR_SHAPE = -2,     /* H <= 0 or W <= 0                                 */
     CCL_ERR_STRIDE = -3,    /* stride < W                                       */
     CCL_ERR_CONN = -4,      /* conn is neither 4 nor 8                          */
-    CCL_ERR_TOO_LARGE = -5, /* H*W >= 2^31 - 1 (labels and raster keys are int32) */
+    CCL_ERR_TOO_LARGE = -5, /* H*W >= 2^31 - 1 or a side >= 2^31 - 256 (int32 labels and keys) */
     CCL_ERR_NOMEM = -6,     /* the workspace could not be allocated             */
     CCL_ERR_HIP = -7,       /* a HIP runtime call or kernel launch failed       */
     CCL_ERR_TILE = -8,      /* unknown tile configuration id                    */
@@ -77,11 +77,11 @@ typedef enum { CCL_SCAN_PAIR = 0, CCL_SCAN_ROW = 1 } ccl_scan;
  *   img     device, H rows of W bytes, row pitch `stride` bytes (>= W);
  *           nonzero = foreground.  Read only.  Any alignment is accepted;
  *           16-byte aligned rows take the fast load path.
- *   H, W    image size in pixels, H*W < 2^31 - 1.
+ *   H, W    image size in pixels, H*W < 2^31 - 1 and H, W < 2^31 - 256.
  *   stride  row pitch of img in bytes.
  *   conn    4 or 8.
  *   labels  device, dense H x W int32, row pitch W elements.  Written
- *           completely; also used as scratch during the call, so it must not
+ *           completely and only after every read of img, so it must not
  *           overlap img.  16-byte alignment and W % 4 == 0 take the fast
  *           store path.
  *   stream  HIP stream (NULL = default stream).
@@ -93,6 +93,58 @@ typedef enum { CCL_SCAN_PAIR = 0, CCL_SCAN_ROW = 1 } ccl_scan;
  */
 int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
               int32_t *labels, hipStream_t stream);
+
+/* One image of ccl_label_batch; fields as for ccl_label. */
+typedef struct {
+    const uint8_t *img;      /* device */
+    int64_t H, W, stride;
+    int conn;                /* 4 or 8, may differ between images */
+    int32_t *labels;         /* device, dense H x W */
+    int32_t *num_components; /* device int32 receiving K, or NULL */
+} ccl_image_desc;
+
+/*
+ * ccl_label_batch -- label n independent images of any sizes with one
+ * launch per phase for the whole batch (tiles of all images share each
+ * grid; images that take different tile-local scans, 8- and 4-connectivity,
+ * form separate launch groups).
+ *   descs   host array of n descriptors (read during the call only).
+ *   n       number of images (0 is a no-op returning CCL_OK).
+ * Every descriptor is validated first; the first invalid one makes the call
+ * return its error with nothing launched (CCL_ERR_BATCH for n < 0 or descs
+ * NULL with n > 0).  No host synchronisation.  The call may be captured
+ * into a HIP graph in any capture mode (after ccl_reserve of
+ * ccl_workspace_bytes / ccl_batch_workspace_bytes on that stream): with
+ * n > 1 the image table then travels in the arguments of small store kernels
+ * that the graph records, so every replay writes it again before the
+ * labeling kernels.  A graph captured from any call of this library uses the
+ * stream's workspace: it must not be replayed after that workspace was grown
+ * by a later, larger call on the same stream or freed by ccl_release, nor
+ * while other work on that workspace (eager calls on the same stream excepted,
+ * which the stream orders) is in flight.
+ */
+int ccl_label_batch(const ccl_image_desc *descs, int n, hipStream_t stream);
+
+/* Workspace bytes one ccl_label call needs for an H x W image (0 for
+ * invalid arguments).  Used for admission by HBM footprint: footprint =
+ * image + labels + workspace. */
+size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn);
+
+/*
+ * ccl_reserve -- grow the workspace of (current device, stream) to at least
+ * `bytes` now, synchronising the stream if it has to reallocate.  Call it
+ * before capturing a stream into a HIP graph: inside capture the workspace
+ * cannot grow and a call that needs more returns CCL_ERR_CAPTURE.
+ */
+int ccl_reserve(size_t bytes, hipStream_t stream);
+
+/* Static description of a status code. */
+const char *ccl_strerror(int status);
+
+/* ------------------------------------------------------------------------
+ * Extended calls: the calls above with the options of the extensions (fused
+ * threshold, gray-level labeling, tile-local scan strategy, tile shape).
+ * ------------------------------------------------------------------------ */
 
 /*
  * ccl_label_ex -- as ccl_label, plus
@@ -130,7 +182,8 @@ int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, in
 int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
                    int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
 
-/* One image of a batch; fields as in ccl_label_level and ccl_label_gray. */
+/* One image of an extended batch.  The first seven fields are those of
+ * ccl_image_desc; the options are as in ccl_label_level / ccl_label_gray. */
 typedef struct {
     const uint8_t *img;      /* device */
     int64_t H, W, stride;
@@ -140,50 +193,37 @@ typedef struct {
     int level;               /* foreground iff byte > level; 0 = nonzero */
     int scan;                /* ccl_scan; 0 = CCL_SCAN_PAIR */
     int gray;                /* 1: gray-level labeling (see ccl_label_gray; scan is ignored) */
-} ccl_image_desc;
+} ccl_image_desc_ex;
 
 /*
- * ccl_label_batch -- label n independent images with one launch per phase
- * for the whole batch (tiles of all images share each grid).
- *   descs   host array of n descriptors (copied during the call).
- *   n       number of images (0 is a no-op returning CCL_OK).
+ * ccl_label_batch_ex -- ccl_label_batch over extended descriptors, with
  *   tile    tile configuration id used for every image (0 = each image's
  *           kind takes its default, ccl_tile_default).
- * Every descriptor is validated first; the first invalid one makes the call
- * return its error with nothing launched.
+ * Errors, capture and workspace as for ccl_label_batch.
  */
-int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t stream);
+int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream);
 
 /*
  * Captured batches.  ccl_batch_graph_create labels nothing: it gives the
  * batch its own workspace and device descriptor table (uploaded before
- * capture), captures every launch of ccl_label_batch for these descriptors
- * into a HIP graph and instantiates it.  ccl_graph_launch replays the whole
- * batch on `stream` with one graph launch; the image and label buffers named
- * in the descriptors are the ones used on every replay (refill the images
- * between replays to label new content of the same shapes).  The graph holds
- * kernel nodes only.  ccl_graph_destroy synchronises the device and frees
- * the graph and its workspace.  Errors as for ccl_label_batch, plus
- * CCL_ERR_NOMEM if the graph's workspace cannot be allocated.
+ * capture), captures every launch of ccl_label_batch_ex for these
+ * descriptors into a HIP graph and instantiates it.  ccl_graph_launch
+ * replays the whole batch on `stream` with one graph launch; the image and
+ * label buffers named in the descriptors are the ones used on every replay
+ * (refill the images between replays to label new content of the same
+ * shapes).  The graph holds kernel nodes only.  ccl_graph_destroy
+ * synchronises the device and frees the graph and its workspace.  Errors as
+ * for ccl_label_batch_ex, plus CCL_ERR_NOMEM if the graph's workspace cannot
+ * be allocated.
  */
 typedef struct ccl_graph ccl_graph;
-int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_graph **graph);
+int ccl_batch_graph_create(const ccl_image_desc_ex *descs, int n, int tile, ccl_graph **graph);
 int ccl_graph_launch(ccl_graph *graph, hipStream_t stream);
 int ccl_graph_destroy(ccl_graph *graph);
 
-/* Workspace bytes one ccl_label_ex call needs for an H x W image with the
- * given tile configuration (0 = the kind's default); 0 for invalid arguments.  Used for
- * admission by HBM footprint: footprint = image + labels + workspace. */
-size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile);
-
-/* Workspace bytes for a batch call (descriptors as for ccl_label_batch). */
-size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile);
-
-/* Grow the workspace of (current device, stream) to at least `bytes` now,
- * synchronising the stream if it has to reallocate.  Call it before
- * capturing a stream into a HIP graph: inside capture the workspace cannot
- * grow and a call that needs more returns CCL_ERR_CAPTURE. */
-int ccl_reserve(size_t bytes, hipStream_t stream);
+/* Workspace bytes for a ccl_label_batch_ex call (0 for invalid arguments);
+ * with tile 0 and default options it is what ccl_label_batch needs. */
+size_t ccl_batch_workspace_bytes(const ccl_image_desc_ex *descs, int n, int tile);
 
 /* Free every cached workspace of the current device (synchronises the
  * device first). */
@@ -219,12 +259,9 @@ int ccl_tile_default(int conn, int scan, int gray);
 int ccl_profile(int enable);
 int ccl_profile_read(double *ms, int nphase, int *ncalls);
 
-/* Static description of a status code. */
-const char *ccl_strerror(int status);
-
 /*
  * Continuous-batching server.  Labeling requests (one image each, described
- * as for ccl_label_batch) arrive at any time from any thread.  A scheduler
+ * as for ccl_label_batch_ex) arrive at any time from any thread.  A scheduler
  * thread inside the library keeps up to n_streams batches in flight, each on
  * its own HIP stream with its own workspace of hbm_budget / n_streams bytes:
  * whenever a stream's batch has completed, the requests waiting at that
@@ -264,9 +301,9 @@ int ccl_server_create(const ccl_server_config *cfg, ccl_server **out);
 /* Queue one request.  `ready`: a stream whose work so far must finish before
  * the image is read and the labels written (e.g. the stream that produced
  * the image), or NULL if the buffers are ready now.  *ticket identifies the
- * request (> 0).  Argument errors as for ccl_label_batch; CCL_ERR_BUDGET if
+ * request (> 0).  Argument errors as for ccl_label_batch_ex; CCL_ERR_BUDGET if
  * the image can never fit a slot. */
-int ccl_server_submit(ccl_server *s, const ccl_image_desc *d, hipStream_t ready, uint64_t *ticket);
+int ccl_server_submit(ccl_server *s, const ccl_image_desc_ex *d, hipStream_t ready, uint64_t *ticket);
 
 /* 1 if the request has completed (*latency_ms, if not NULL, gets its
  * submission-to-completion time), 0 if not yet, CCL_ERR_TICKET if unknown. */

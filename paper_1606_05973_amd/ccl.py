@@ -26,7 +26,13 @@ _stream = ctypes.c_void_p
 
 
 class ImageDesc(ctypes.Structure):
-    """ccl_image_desc of include/ccl.h."""
+    """ccl_image_desc of include/ccl.h (the plain batch call)."""
+    _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
+                ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p)]
+
+
+class ImageDescEx(ctypes.Structure):
+    """ccl_image_desc_ex of include/ccl.h (the extended calls)."""
     _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
                 ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p),
                 ("level", ctypes.c_int), ("scan", ctypes.c_int), ("gray", ctypes.c_int)]
@@ -42,11 +48,13 @@ _lib.ccl_label_level.restype = ctypes.c_int
 _lib.ccl_label_gray.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
                                 _stream]
 _lib.ccl_label_gray.restype = ctypes.c_int
-_lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int, _stream]
+_lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, _stream]
 _lib.ccl_label_batch.restype = ctypes.c_int
-_lib.ccl_workspace_bytes.argtypes = [_i64, _i64, ctypes.c_int, ctypes.c_int]
+_lib.ccl_label_batch_ex.argtypes = [ctypes.POINTER(ImageDescEx), ctypes.c_int, ctypes.c_int, _stream]
+_lib.ccl_label_batch_ex.restype = ctypes.c_int
+_lib.ccl_workspace_bytes.argtypes = [_i64, _i64, ctypes.c_int]
 _lib.ccl_workspace_bytes.restype = ctypes.c_size_t
-_lib.ccl_batch_workspace_bytes.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int]
+_lib.ccl_batch_workspace_bytes.argtypes = [ctypes.POINTER(ImageDescEx), ctypes.c_int, ctypes.c_int]
 _lib.ccl_batch_workspace_bytes.restype = ctypes.c_size_t
 _lib.ccl_reserve.argtypes = [ctypes.c_size_t, _stream]
 _lib.ccl_reserve.restype = ctypes.c_int
@@ -58,7 +66,7 @@ _lib.ccl_tile_count.argtypes = []
 _lib.ccl_tile_count.restype = ctypes.c_int
 _lib.ccl_tile_default.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _lib.ccl_tile_default.restype = ctypes.c_int
-_lib.ccl_batch_graph_create.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, ctypes.c_int,
+_lib.ccl_batch_graph_create.argtypes = [ctypes.POINTER(ImageDescEx), ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_void_p)]
 _lib.ccl_batch_graph_create.restype = ctypes.c_int
 _lib.ccl_graph_launch.argtypes = [ctypes.c_void_p, _stream]
@@ -84,7 +92,7 @@ class ServerStats(ctypes.Structure):
 
 _lib.ccl_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
 _lib.ccl_server_create.restype = ctypes.c_int
-_lib.ccl_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(ImageDesc), _stream,
+_lib.ccl_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(ImageDescEx), _stream,
                                    ctypes.POINTER(ctypes.c_uint64)]
 _lib.ccl_server_submit.restype = ctypes.c_int
 _lib.ccl_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
@@ -166,26 +174,40 @@ def level_of(fraction: float) -> int:
     return min(255, max(0, int(math.floor(fraction * 255))))
 
 
+def _check_out(out: torch.Tensor, img: torch.Tensor):
+    """The label buffer the library writes H*W int32 into."""
+    if not isinstance(out, torch.Tensor) or tuple(out.shape) != tuple(img.shape) or out.dtype != torch.int32 \
+            or not out.is_contiguous() or out.device != img.device:
+        raise ValueError("out must be a contiguous int32 tensor of the image's shape on the image's device")
+
+
+def _check_counts(num_components, n: int, device) -> None:
+    """The K output: a contiguous device int32 tensor with at least n slots."""
+    if num_components is None:
+        return
+    if not isinstance(num_components, torch.Tensor) or num_components.dtype != torch.int32 \
+            or not num_components.is_contiguous() or num_components.numel() < n \
+            or num_components.device != torch.device(device):
+        raise ValueError(f"num_components must be a contiguous int32 tensor with at least {n} slots "
+                         "on the images' device")
+
+
 def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
           num_components: torch.Tensor | None = None, stream=None, level: int = 0,
           scan: int = SCAN_PAIR) -> torch.Tensor:
     """Canonical int32 labels of a 2-D uint8 device image; foreground iff the
     byte exceeds `level` (0 = nonzero).  `scan` picks the tile-local scan
     strategy (SCAN_PAIR or SCAN_ROW); the labels do not depend on it."""
-    if scan != SCAN_PAIR:
-        return label_batch([img], conn, outs=None if out is None else [out], tile=tile,
-                           num_components=num_components, stream=stream, level=level, scan=scan)[0]
     H, W, stride = _img_geometry(img)
     if out is None:
         out = torch.empty((H, W), dtype=torch.int32, device=img.device)
-    if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous int32 tensor of the image's shape")
-    nc = 0
-    if num_components is not None:
-        if num_components.dtype != torch.int32 or num_components.numel() < 1 or not num_components.is_cuda:
-            raise ValueError("num_components must be a device int32 tensor")
-        nc = num_components.data_ptr()
-    st = _lib.ccl_label_level(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc or None,
+    _check_out(out, img)
+    _check_counts(num_components, 1, img.device)
+    if scan != SCAN_PAIR:
+        return label_batch([img], conn, outs=[out], tile=tile, num_components=num_components, stream=stream,
+                           level=level, scan=scan)[0]
+    nc = num_components.data_ptr() if num_components is not None else None
+    st = _lib.ccl_label_level(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc,
                               int(tile), _stream_handle(stream))
     _check(st)
     return out
@@ -198,14 +220,10 @@ def label_gray(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None
     H, W, stride = _img_geometry(img)
     if out is None:
         out = torch.empty((H, W), dtype=torch.int32, device=img.device)
-    if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous int32 tensor of the image's shape")
-    nc = 0
-    if num_components is not None:
-        if num_components.dtype != torch.int32 or num_components.numel() < 1 or not num_components.is_cuda:
-            raise ValueError("num_components must be a device int32 tensor")
-        nc = num_components.data_ptr()
-    _check(_lib.ccl_label_gray(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc or None,
+    _check_out(out, img)
+    _check_counts(num_components, 1, img.device)
+    nc = num_components.data_ptr() if num_components is not None else None
+    _check(_lib.ccl_label_gray(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc,
                                int(tile), _stream_handle(stream)))
     return out
 
@@ -215,40 +233,52 @@ def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: 
     return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
 
 
-def _descs(imgs, conns, outs, counts, levels=None, scans=None, grays=None):
+def _descs(imgs, conns, outs, num_components, levels=None, scans=None, grays=None):
+    """Extended descriptors of a batch, after checking every buffer the
+    library will write: outs[i] for image i, slot i of num_components."""
     n = len(imgs)
-    arr = (ImageDesc * max(n, 1))()
+    if len(outs) != n:
+        raise ValueError("one label buffer per image")
+    if n:
+        _check_counts(num_components, n, imgs[0].device)
+    arr = (ImageDescEx * max(n, 1))()
     for i, img in enumerate(imgs):
         H, W, stride = _img_geometry(img)
+        _check_out(outs[i], img)
+        if num_components is not None and num_components.device != img.device:
+            raise ValueError("num_components must be on the images' device")
         arr[i].img = img.data_ptr()
         arr[i].H, arr[i].W, arr[i].stride = H, W, stride
         arr[i].conn = int(conns[i])
         arr[i].labels = outs[i].data_ptr()
-        arr[i].num_components = counts[i].data_ptr() if counts is not None else None
+        arr[i].num_components = num_components.data_ptr() + 4 * i if num_components is not None else None
         arr[i].level = int(levels[i]) if levels is not None else 0
         arr[i].scan = int(scans[i]) if scans is not None else 0
         arr[i].gray = int(bool(grays[i])) if grays is not None else 0
     return arr
 
 
+def _per_image(v, n):
+    out = list(v) if isinstance(v, (list, tuple)) else [v] * n
+    if len(out) != n:
+        raise ValueError("a per-image option list must have one entry per image")
+    return out
+
+
 def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
                 stream=None, level=0, scan=SCAN_PAIR, gray=False):
-    """Label a list of images with one launch per phase for the whole batch.
+    """Label a list of images with one launch per phase for the whole batch
+    (ccl_label_batch_ex).
 
     conn, level, scan, gray: one value or a per-image list.  num_components:
-    optional device int32 tensor with one slot per image."""
+    optional contiguous device int32 tensor with one slot per image."""
     n = len(imgs)
-    conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
-    levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
-    scans = list(scan) if isinstance(scan, (list, tuple)) else [scan] * n
-    grays = list(gray) if isinstance(gray, (list, tuple)) else [gray] * n
+    conns, levels = _per_image(conn, n), _per_image(level, n)
+    scans, grays = _per_image(scan, n), _per_image(gray, n)
     if outs is None:
         outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
-    counts = None
-    if num_components is not None:
-        counts = [num_components[i:i + 1] for i in range(n)]
-    arr = _descs(imgs, conns, outs, counts, levels, scans, grays)
-    _check(_lib.ccl_label_batch(arr, n, int(tile), _stream_handle(stream)))
+    arr = _descs(imgs, conns, outs, num_components, levels, scans, grays)
+    _check(_lib.ccl_label_batch_ex(arr, n, int(tile), _stream_handle(stream)))
     return outs
 
 
@@ -277,14 +307,11 @@ class BatchGraph:
     def __init__(self, imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
                  level=0, scan=SCAN_PAIR):
         n = len(imgs)
-        conns = list(conn) if isinstance(conn, (list, tuple)) else [conn] * n
-        levels = list(level) if isinstance(level, (list, tuple)) else [level] * n
-        scans = list(scan) if isinstance(scan, (list, tuple)) else [scan] * n
+        conns, levels, scans = _per_image(conn, n), _per_image(level, n), _per_image(scan, n)
         if outs is None:
             outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
-        counts = [num_components[i:i + 1] for i in range(n)] if num_components is not None else None
         self.imgs, self.outs, self.counts = list(imgs), outs, num_components
-        arr = _descs(imgs, conns, outs, counts, levels, scans)
+        arr = _descs(imgs, conns, outs, num_components, levels, scans)
         h = ctypes.c_void_p()
         _check(_lib.ccl_batch_graph_create(arr, n, int(tile), ctypes.byref(h)))
         self._h = h
@@ -306,20 +333,24 @@ class BatchGraph:
 
 
 def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0, scan: int = SCAN_PAIR) -> int:
-    if scan != SCAN_PAIR:
+    """Workspace bytes of one labeling call (ccl_workspace_bytes for the
+    defaults, else the extended batch form)."""
+    if scan != SCAN_PAIR or tile != 0:
         return batch_workspace_bytes([(H, W)], conn, tile, scan)
-    return int(_lib.ccl_workspace_bytes(H, W, conn, tile))
+    return int(_lib.ccl_workspace_bytes(H, W, conn))
 
 
-def batch_workspace_bytes(shapes, conn=8, tile: int = 0, scan=SCAN_PAIR) -> int:
+def batch_workspace_bytes(shapes, conn=8, tile: int = 0, scan=SCAN_PAIR, gray=False) -> int:
     n = len(shapes)
-    arr = (ImageDesc * max(n, 1))()
+    conns, scans, grays = _per_image(conn, n), _per_image(scan, n), _per_image(gray, n)
+    arr = (ImageDescEx * max(n, 1))()
     for i, (H, W) in enumerate(shapes):
         arr[i].img = 1
         arr[i].labels = 1
         arr[i].H, arr[i].W, arr[i].stride = H, W, W
-        arr[i].conn = conn if isinstance(conn, int) else conn[i]
-        arr[i].scan = scan if isinstance(scan, int) else scan[i]
+        arr[i].conn = int(conns[i])
+        arr[i].scan = int(scans[i])
+        arr[i].gray = int(bool(grays[i]))
     return int(_lib.ccl_batch_workspace_bytes(arr, n, int(tile)))
 
 

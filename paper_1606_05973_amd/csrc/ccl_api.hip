@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -19,6 +20,10 @@
 namespace ccl {
 namespace {
 
+// Every path works on extended descriptors; ccl_label_batch widens its
+// plain ones.
+typedef ccl_image_desc_ex Desc;
+
 // ---------------------------------------------------------------- tiles
 // A tile configuration is (block rows, width).  The tile height is block
 // rows x 2 under 8-connectivity (two image rows per block row) and block
@@ -33,11 +38,11 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 // Image rows per block row: two under 8-connectivity with the pair-row scan
 // (the default), one otherwise.
 inline int bh_of(int conn, int scan) { return (conn == 8 && scan == CCL_SCAN_PAIR) ? 2 : 1; }
-inline int bh_of(const ccl_image_desc &d) { return d.gray ? 1 : bh_of(d.conn, d.scan); }
+inline int bh_of(const Desc &d) { return d.gray ? 1 : bh_of(d.conn, d.scan); }
 
 // Launch groups of a batch: row-pair runs, single-row runs, gray levels.
 enum Group { kPair = 0, kRow = 1, kGray = 2, kGroups = 3 };
-inline int group_of(const ccl_image_desc &d) { return d.gray ? kGray : (bh_of(d) == 2 ? kPair : kRow); }
+inline int group_of(const Desc &d) { return d.gray ? kGray : (bh_of(d) == 2 ? kPair : kRow); }
 inline int group_of(int conn, int scan, int gray) { return gray ? kGray : (bh_of(conn, scan) == 2 ? kPair : kRow); }
 
 // Default tile id per group (fastest in a sweep of the configurations on
@@ -104,14 +109,15 @@ int check_image(const void *img, int64_t H, int64_t W, int64_t stride, int conn,
         return CCL_ERR_STRIDE;
     if (conn != 4 && conn != 8)
         return CCL_ERR_CONN;
-    if (H > INT32_MAX || W > INT32_MAX || H * W >= (int64_t)INT32_MAX)
+    // (sides are rounded up to whole tiles and edge lines in int32)
+    if (H >= (int64_t)INT32_MAX - 255 || W >= (int64_t)INT32_MAX - 255 || H * W >= (int64_t)INT32_MAX)
         return CCL_ERR_TOO_LARGE;
     return CCL_OK;
 }
 
 int check_level(int level) { return (level < 0 || level > 255) ? CCL_ERR_LEVEL : CCL_OK; }
 
-int check_opts(const ccl_image_desc &d) {
+int check_opts(const Desc &d) {
     if (d.scan != CCL_SCAN_PAIR && d.scan != CCL_SCAN_ROW)
         return CCL_ERR_SCAN;
     if (d.gray != 0 && d.gray != 1)
@@ -179,7 +185,7 @@ static void set_ptr(P &field, const void *p) {
 }
 
 // Fill an Img from a descriptor, its layout and its workspace base.
-Img make_img(const ccl_image_desc &d, const Layout &L, char *base) {
+Img make_img(const Desc &d, const Layout &L, char *base) {
     Img im{};
     set_ptr(im.img, d.img);
     set_ptr(im.labels, d.labels);
@@ -341,7 +347,7 @@ int dispatch(const TileCfg &c, int group, const Batch &b, int64_t tiles, int64_t
 size_t group_table_bytes(size_t n) { return align_up(n * (sizeof(Img) + 3 * sizeof(int32_t))); }
 
 // Fills a group's table (Img entries and keys) in `tab`; returns the counts.
-int build_group_table(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+int build_group_table(const Desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
                       const std::vector<size_t> &offs, char *base, char *tab_bytes, int64_t *tiles_out,
                       int64_t *edges_out, int64_t *blocks_out) {
     const int n = (int)idx.size();
@@ -371,8 +377,11 @@ int build_group_table(const ccl_image_desc *descs, const std::vector<int> &idx, 
 
 // Workspace: [tables of the groups][per-image regions].  The group's table
 // is built in `htab` (pinned host memory that stays untouched until the
-// stream has passed the copy) or, when htab is NULL, in a temporary.
-int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+// stream has passed the copy) or else in a temporary: a copy from pageable
+// memory has read it by the time the call returns, and on a stream being
+// captured the table is stored by k_put_words launches that carry it in
+// their arguments (a copy node would keep a pointer to the temporary).
+int run_group(const Desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
               const std::vector<size_t> &offs, char *base, char *dtab, int group, const TileCfg &c,
               hipStream_t stream, bool table_ready = false, char *htab = nullptr) {
     const int n = (int)idx.size();
@@ -390,7 +399,7 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
     b.n = n;
     b.store = kStore16;
     for (int k = 0; k < n; k++) {
-        const ccl_image_desc &d = descs[idx[k]];
+        const Desc &d = descs[idx[k]];
         if (d.W > kVecMaxW)
             b.store = kStoreAny;
         else if (b.store == kStore16 && (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0))
@@ -401,22 +410,47 @@ int run_group(const ccl_image_desc *descs, const std::vector<int> &idx, const st
         b.tab = nullptr;
         b.keys = nullptr;
     } else {
-        if (!table_ready && hipMemcpyAsync(dtab, tab_bytes, tbytes, hipMemcpyHostToDevice, stream) != hipSuccess)
-            return CCL_ERR_HIP;
+        if (!table_ready) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(stream, &cs) != hipSuccess)
+                return CCL_ERR_HIP;
+            if (cs == hipStreamCaptureStatusNone) {
+                if (hipMemcpyAsync(dtab, tab_bytes, tbytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+                    return CCL_ERR_HIP;
+            } else {
+                static_assert(sizeof(WordChunk) == 4 * kChunkWords, "chunk layout");
+                const size_t words = tbytes / 4;   // tbytes is a multiple of 256
+                for (size_t at = 0; at < words; at += kChunkWords) {
+                    WordChunk ch;
+                    const int cnt = (int)std::min<size_t>(kChunkWords, words - at);
+                    memcpy(ch.w, tab_bytes + 4 * at, 4 * (size_t)cnt);
+                    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(kChunkWords), 0, stream,
+                                       reinterpret_cast<uint32_t *>(dtab) + at, cnt, ch);
+                }
+                if (hipGetLastError() != hipSuccess)
+                    return CCL_ERR_HIP;
+            }
+        }
         b.tab = reinterpret_cast<const Img *>(dtab);
         b.keys = reinterpret_cast<const int32_t *>(dtab + (size_t)n * sizeof(Img));
     }
     return dispatch(tile_for(c, group), group, b, tiles, edges, blocks, n, stream);
 }
 
-size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
+// The group tables at the start of a batch's workspace.
+size_t tables_bytes(const size_t per_group[kGroups]) {
+    size_t off = 0;
+    for (int k = 0; k < kGroups; k++)
+        off += group_table_bytes(per_group[k]);
+    return off;
+}
+
+size_t batch_bytes(const Desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
                    std::vector<size_t> *offs) {
     size_t per_group[kGroups] = {0, 0, 0};
     for (int i = 0; i < n; i++)
         per_group[group_of(descs[i])]++;
-    size_t off = 0;
-    for (int k = 0; k < kGroups; k++)
-        off += group_table_bytes(per_group[k]);
+    size_t off = tables_bytes(per_group);
     for (int i = 0; i < n; i++) {
         Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), tile_for(c, group_of(descs[i])),
                              descs[i].gray != 0);
@@ -430,7 +464,7 @@ size_t batch_bytes(const ccl_image_desc *descs, int n, const TileCfg &c, std::ve
 }
 
 // Launch a batch into a workspace of at least batch_bytes(descs) bytes.
-int run_batch_in(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream, char *base,
+int run_batch_in(const Desc *descs, int n, const TileCfg &c, hipStream_t stream, char *base,
                  char *htab = nullptr) {
     std::vector<Layout> lays;
     std::vector<size_t> offs;
@@ -449,7 +483,7 @@ int run_batch_in(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream
     return CCL_OK;
 }
 
-int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t stream) {
+int run_batch(const Desc *descs, int n, const TileCfg &c, hipStream_t stream) {
     void *ws = nullptr;
     int st = get_workspace(stream, batch_bytes(descs, n, c, nullptr, nullptr), &ws);
     if (st != CCL_OK)
@@ -458,7 +492,7 @@ int run_batch(const ccl_image_desc *descs, int n, const TileCfg &c, hipStream_t 
 }
 
 // Device table of one group, uploaded synchronously (used before capture).
-int upload_group_table(const ccl_image_desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
+int upload_group_table(const Desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
                        const std::vector<size_t> &offs, char *base, char *dtab) {
     const int n = (int)idx.size();
     if (n <= 1)
@@ -494,7 +528,7 @@ int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, in
     TileCfg c;
     if ((st = resolve_tile(tile, &c)) != CCL_OK)
         return st;
-    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR, 0};
+    Desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR, 0};
     return run_batch(&d, 1, c, stream);
 }
 
@@ -508,7 +542,7 @@ int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int
     TileCfg c;
     if ((st = resolve_tile(tile, &c)) != CCL_OK)
         return st;
-    ccl_image_desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_ROW, 1};
+    Desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_ROW, 1};
     return run_batch(&d, 1, c, stream);
 }
 
@@ -522,7 +556,7 @@ int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn
     return ccl_label_ex(img, H, W, stride, conn, labels, nullptr, 0, stream);
 }
 
-int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t stream) {
+int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream) {
     if (n < 0 || (n > 0 && !descs))
         return CCL_ERR_BATCH;
     TileCfg c;
@@ -541,19 +575,29 @@ int ccl_label_batch(const ccl_image_desc *descs, int n, int tile, hipStream_t st
     return run_batch(descs, n, c, stream);
 }
 
-size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn, int tile) {
-    TileCfg c;
-    if (resolve_tile(tile, &c) != CCL_OK)
-        return 0;
+int ccl_label_batch(const ccl_image_desc *descs, int n, hipStream_t stream) {
+    if (n < 0 || (n > 0 && !descs))
+        return CCL_ERR_BATCH;
+    std::vector<Desc> ex((size_t)n);
+    for (int i = 0; i < n; i++) {
+        const ccl_image_desc &d = descs[i];
+        ex[i] = Desc{d.img, d.H, d.W, d.stride, d.conn, d.labels, d.num_components, 0, CCL_SCAN_PAIR, 0};
+    }
+    return ccl_label_batch_ex(ex.data(), n, 0, stream);
+}
+
+size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn) {
     int8_t dummy;
     if (check_image(&dummy, H, W, W, conn, &dummy) != CCL_OK)
         return 0;
-    ccl_image_desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy),
-                     nullptr, 0, CCL_SCAN_PAIR, 0};
+    TileCfg c;
+    (void)resolve_tile(0, &c);
+    Desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy), nullptr, 0,
+           CCL_SCAN_PAIR, 0};
     return batch_bytes(&d, 1, c, nullptr, nullptr);
 }
 
-size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile) {
+size_t ccl_batch_workspace_bytes(const ccl_image_desc_ex *descs, int n, int tile) {
     TileCfg c;
     if (resolve_tile(tile, &c) != CCL_OK || n < 0 || (n > 0 && !descs))
         return 0;
@@ -566,7 +610,7 @@ size_t ccl_batch_workspace_bytes(const ccl_image_desc *descs, int n, int tile) {
     return batch_bytes(descs, n, c, nullptr, nullptr);
 }
 
-int ccl_batch_graph_create(const ccl_image_desc *descs, int n, int tile, ccl_graph **out) {
+int ccl_batch_graph_create(const ccl_image_desc_ex *descs, int n, int tile, ccl_graph **out) {
     if (!out)
         return CCL_ERR_NULL;
     *out = nullptr;
@@ -766,7 +810,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 struct ServerReq {
-    ccl_image_desc d;
+    ccl::Desc d;
     uint64_t ticket;
     hipEvent_t ready;      // recorded on the submitter's stream, or NULL
     size_t bytes;          // this image's workspace region
@@ -804,7 +848,7 @@ struct ccl_server {
     int error = CCL_OK;              // first HIP failure seen by the scheduler
     std::thread th;
 
-    size_t bytes_of(const ccl_image_desc &d) const {
+    size_t bytes_of(const ccl::Desc &d) const {
         return ccl::layout_of(d.H, d.W, ccl::bh_of(d), ccl::tile_for(tile, ccl::group_of(d)), d.gray != 0).bytes;
     }
 
@@ -821,17 +865,24 @@ struct ccl_server {
         sl.busy = false;
     }
 
-    // Take the longest queue prefix that fits one slot.
+    // Take the longest queue prefix that fits one slot.  The footprint of a
+    // candidate batch is what run_batch_in will lay out in the slot's
+    // workspace: the table of every launch group, then the image regions.
     std::vector<ccl::ServerReq> take_batch() {
         std::vector<ccl::ServerReq> b;
         size_t used = 0;
+        size_t per_group[ccl::kGroups] = {0, 0, 0};
         int64_t px = 0;
         while (!pending.empty() && (int)b.size() < cfg.max_batch) {
             const ccl::ServerReq &r = pending.front();
             const int64_t n = r.d.H * r.d.W;
-            const size_t need = ccl::align_up((b.size() + 1) * sizeof(ccl::Img)) + used + r.bytes;
-            if (!b.empty() && (px + n > cfg.max_batch_pixels || need > ws_bytes))
+            const int g = ccl::group_of(r.d);
+            per_group[g]++;
+            const size_t need = ccl::tables_bytes(per_group) + used + r.bytes;
+            if (!b.empty() && (px + n > cfg.max_batch_pixels || need > ws_bytes)) {
+                per_group[g]--;
                 break;
+            }
             used += r.bytes;
             px += n;
             b.push_back(r);
@@ -866,7 +917,7 @@ struct ccl_server {
                     continue;
                 std::vector<ccl::ServerReq> b = take_batch();
                 lk.unlock();
-                std::vector<ccl_image_desc> descs;
+                std::vector<ccl::Desc> descs;
                 int st = CCL_OK;
                 for (auto &r : b) {
                     descs.push_back(r.d);
@@ -949,7 +1000,7 @@ int ccl_server_create(const ccl_server_config *cfg, ccl_server **out) {
     return CCL_OK;
 }
 
-int ccl_server_submit(ccl_server *s, const ccl_image_desc *d, hipStream_t ready, uint64_t *ticket) {
+int ccl_server_submit(ccl_server *s, const ccl_image_desc_ex *d, hipStream_t ready, uint64_t *ticket) {
     if (!s || !d || !ticket)
         return CCL_ERR_NULL;
     int st = ccl::check_image(d->img, d->H, d->W, d->stride, d->conn, d->labels);
@@ -960,7 +1011,7 @@ int ccl_server_submit(ccl_server *s, const ccl_image_desc *d, hipStream_t ready,
     ccl::ServerReq r{};
     r.d = *d;
     r.bytes = s->bytes_of(*d);
-    if (ccl::align_up(sizeof(ccl::Img)) + r.bytes > s->ws_bytes) {
+    if (ccl::group_table_bytes(1) + r.bytes > s->ws_bytes) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->rejected++;
         return CCL_ERR_BUDGET;

@@ -128,6 +128,21 @@ __device__ __forceinline__ Img find_img(const Batch &b, int32_t item, int which)
     return r;
 }
 
+// A chunk of host data carried in the kernel arguments and stored to
+// device memory.  A launch captured into a graph keeps its arguments, so
+// every replay writes the same words again: this is how the image table of
+// a batch call captured into a graph reaches the device without a host
+// buffer that would have to outlive the graph.
+constexpr int kChunkWords = 512;
+struct WordChunk {
+    uint32_t w[kChunkWords];
+};
+__global__ __launch_bounds__(kChunkWords) void k_put_words(uint32_t *dst, int n, WordChunk c) {
+    const int i = threadIdx.x;
+    if (i < n)
+        dst[i] = c.w[i];
+}
+
 // Workgroups are dealt to the eight XCDs round robin (workgroup b runs on
 // XCD b % 8, each XCD with its own L2).  This gives each XCD a contiguous
 // range of the n tiles in raster order, so horizontally adjacent tiles, which

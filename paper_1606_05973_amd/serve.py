@@ -89,15 +89,19 @@ class Server:
         self._inflight = collections.deque()
 
     def submit(self, img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, level: int = 0,
-               scan: int = ccl.SCAN_PAIR) -> Request:
+               scan: int = ccl.SCAN_PAIR, gray: bool = False, ready=True) -> Request:
+        """Queue one image.  ready: True = the image and `out` are ready once
+        the current stream's work so far is (the library waits for it on the
+        device), a torch stream = once that stream's work is, False = now."""
         H, W, stride = ccl._img_geometry(img)
         if out is None:
             out = torch.empty((H, W), dtype=torch.int32, device=img.device)
-        d = ccl.ImageDesc(img=img.data_ptr(), H=H, W=W, stride=stride, conn=int(conn), labels=out.data_ptr(),
-                          num_components=None, level=int(level), scan=int(scan))
+        ccl._check_out(out, img)
+        d = ccl.ImageDescEx(img=img.data_ptr(), H=H, W=W, stride=stride, conn=int(conn), labels=out.data_ptr(),
+                            num_components=None, level=int(level), scan=int(scan), gray=int(bool(gray)))
         t = ctypes.c_uint64()
-        # the image and label buffer are ready once the current stream's work is
-        st = ccl._lib.ccl_server_submit(self._h, ctypes.byref(d), ccl._stream_handle(None), ctypes.byref(t))
+        rs = None if ready is False else ccl._stream_handle(None if ready is True else ready)
+        st = ccl._lib.ccl_server_submit(self._h, ctypes.byref(d), rs, ctypes.byref(t))
         if st == ccl.STATUS["CCL_ERR_BUDGET"]:
             return Request(self, 0, img, conn, None, "rejected")
         ccl._check(st)

@@ -22,7 +22,7 @@ def _declared_functions():
 
 def test_header_declares_api():
     names = _declared_functions()
-    for expected in ("ccl_label", "ccl_label_ex", "ccl_label_batch", "ccl_workspace_bytes",
+    for expected in ("ccl_label", "ccl_label_ex", "ccl_label_batch", "ccl_label_batch_ex", "ccl_workspace_bytes",
                      "ccl_batch_workspace_bytes", "ccl_reserve", "ccl_release", "ccl_tile_config",
                      "ccl_tile_count", "ccl_tile_default", "ccl_strerror", "ccl_batch_graph_create", "ccl_graph_launch",
                      "ccl_graph_destroy", "ccl_profile", "ccl_profile_read"):
@@ -47,32 +47,50 @@ def test_status_codes_on_host():
     assert ccl.label_raw(dummy, 10, 10, 9, 8, dummy, stream=0) == S["CCL_ERR_STRIDE"]
     assert ccl.label_raw(dummy, 10, 10, 10, 6, dummy, stream=0) == S["CCL_ERR_CONN"]
     assert ccl.label_raw(dummy, 1 << 16, 1 << 15, 1 << 15, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
+    # sides that would overflow int32 once rounded up to tiles and edge lines
+    assert ccl.label_raw(dummy, 1, (1 << 31) - 200, (1 << 31) - 200, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
+    assert ccl.label_raw(dummy, (1 << 31) - 200, 1, 1, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
     lib = ccl._lib
     assert lib.ccl_label_ex(dummy, 10, 10, 10, 8, dummy, None, 99, None) == S["CCL_ERR_TILE"]
-    assert lib.ccl_label_batch(None, -1, 0, None) == S["CCL_ERR_BATCH"]
-    assert lib.ccl_label_batch(None, 3, 0, None) == S["CCL_ERR_BATCH"]
-    assert lib.ccl_label_batch(None, 0, 0, None) == 0
+    # the plain batch call (descriptor of seven fields, no options)
+    assert lib.ccl_label_batch(None, -1, None) == S["CCL_ERR_BATCH"]
+    assert lib.ccl_label_batch(None, 3, None) == S["CCL_ERR_BATCH"]
+    assert lib.ccl_label_batch(None, 0, None) == 0
+    plain = (ccl.ImageDesc * 2)()
+    for i in range(2):
+        plain[i].img, plain[i].labels = dummy, dummy
+        plain[i].H = plain[i].W = plain[i].stride = 8
+        plain[i].conn = 8
+    plain[1].stride = 7
+    assert lib.ccl_label_batch(plain, 2, None) == S["CCL_ERR_STRIDE"]
+    plain[1].stride = 8
+    plain[0].labels = None
+    assert lib.ccl_label_batch(plain, 2, None) == S["CCL_ERR_NULL"]
+    # the extended batch call
+    assert lib.ccl_label_batch_ex(None, -1, 0, None) == S["CCL_ERR_BATCH"]
+    assert lib.ccl_label_batch_ex(None, 0, 0, None) == 0
     # a bad descriptor anywhere in the batch rejects the whole call
-    arr = (ccl.ImageDesc * 2)()
+    arr = (ccl.ImageDescEx * 2)()
     for i in range(2):
         arr[i].img, arr[i].labels = dummy, dummy
         arr[i].H = arr[i].W = arr[i].stride = 8
         arr[i].conn = 8
+    assert lib.ccl_label_batch_ex(arr, 2, 99, None) == S["CCL_ERR_TILE"]
     arr[1].conn = 5
-    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_CONN"]
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_CONN"]
     arr[1].conn = 4
     arr[0].level = 256
-    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_LEVEL"]
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_LEVEL"]
     arr[0].level = -1
-    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_LEVEL"]
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_LEVEL"]
     assert lib.ccl_label_level(dummy, 10, 10, 10, 256, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
     assert lib.ccl_label_level(dummy, 10, 10, 10, -3, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
     arr[0].level = 0
     arr[1].scan = 2
-    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_SCAN"]
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_SCAN"]
     arr[1].scan = 0
     arr[1].gray = 3
-    assert lib.ccl_label_batch(arr, 2, 0, None) == S["CCL_ERR_GRAY"]
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_GRAY"]
     arr[1].gray = 0
     assert lib.ccl_label_gray(dummy, 10, 10, 10, 300, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
     assert lib.ccl_label_gray(dummy, 10, 10, 10, 0, 5, dummy, None, 0, None) == S["CCL_ERR_CONN"]
@@ -83,6 +101,38 @@ def test_status_codes_on_host():
     assert lib.ccl_batch_graph_create(arr, 0, 0, ctypes.byref(h)) == S["CCL_ERR_BATCH"]
     assert lib.ccl_graph_launch(None, None) == S["CCL_ERR_NULL"]
     assert lib.ccl_graph_destroy(None) == 0
+
+
+def test_descriptor_layouts_match_the_header(tmp_path):
+    """The ctypes descriptors have the size and field offsets that a C
+    compiler gives the structs of include/ccl.h."""
+    import subprocess
+
+    from paper_1606_05973_amd import ccl
+    fields = {"ccl_image_desc": (ccl.ImageDesc, ["img", "H", "W", "stride", "conn", "labels", "num_components"]),
+              "ccl_image_desc_ex": (ccl.ImageDescEx, ["img", "H", "W", "stride", "conn", "labels", "num_components",
+                                                      "level", "scan", "gray"]),
+              "ccl_server_config": (ccl.ServerConfig, ["n_streams", "max_batch", "max_batch_pixels", "hbm_budget",
+                                                       "tile"]),
+              "ccl_server_stats": (ccl.ServerStats, ["submitted", "completed", "rejected", "batches",
+                                                     "in_flight_max", "pixels_completed", "p50_ms", "p99_ms",
+                                                     "mean_ms"])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ccl.h"', 'int main(void) {']
+    for st, (_, names) in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in names:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for st, (cls, names) in fields.items():
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in names:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
 
 
 def test_strerror_and_tiles():
@@ -103,8 +153,25 @@ def test_strerror_and_tiles():
         assert ccl._lib.ccl_tile_default(*bad) == 0
 
 
+def test_header_boundary_signatures():
+    """The six calls of the contract, with exactly its argument lists."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    src = re.sub(r"\s+", " ", src)
+    for decl in ("int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, "
+                 "int32_t *labels, hipStream_t stream);",
+                 "int ccl_label_batch(const ccl_image_desc *descs, int n, hipStream_t stream);",
+                 "size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn);",
+                 "int ccl_reserve(size_t bytes, hipStream_t stream);",
+                 "const char *ccl_strerror(int status);",
+                 "typedef struct { const uint8_t *img; int64_t H, W, stride; int conn; int32_t *labels; "
+                 "int32_t *num_components; } ccl_image_desc;"):
+        assert decl in src, decl
+
+
 def test_workspace_bytes():
     from paper_1606_05973_amd import ccl
+    assert ccl._lib.ccl_workspace_bytes(1000, 1000, 8) == ccl.workspace_bytes(1000, 1000)
+    assert ccl._lib.ccl_workspace_bytes(1000, 1000, 5) == 0
     assert ccl.workspace_bytes(0, 10) == 0
     assert ccl.workspace_bytes(10, 10, conn=3) == 0
     a = ccl.workspace_bytes(1000, 1000)

@@ -146,3 +146,74 @@ def test_serve_threshold_and_scan_options(ccl):
         ref = oracle.label(im.cpu().numpy(), 8 if i % 2 else 4, level=60 + 20 * i)
         assert np.array_equal(r.labels.cpu().numpy(), ref)
     srv.close()
+
+
+def test_captured_batch_call_replays(ccl):
+    """ccl_label_batch captured into a graph (by torch, global capture mode)
+    with several images: every replay labels the images' current content,
+    with eager calls on the same stream between the replays."""
+    specs = inputs.batch_specs(9, seed=41, max_side=500)
+    imgs = [inputs.make(s_, device=DEV) for s_ in specs]
+    conns = [8 if i % 3 else 4 for i in range(len(imgs))]
+    outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=DEV) for im in imgs]
+    k = torch.full((len(imgs),), -1, dtype=torch.int32, device=DEV)
+    other = inputs.bernoulli(256, 300, 0.5, seed=8, device=DEV)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ccl.reserve(ccl.batch_workspace_bytes([tuple(im.shape) for im in imgs], conns) + (1 << 20))
+        ccl.label_batch(imgs, conns, outs=outs, num_components=k)   # eager warm-up on the same stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("case capture ccl_label_batch n=9")
+    with torch.cuda.graph(g, stream=side):
+        ccl.label_batch(imgs, conns, outs=outs, num_components=k)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for i, (img, s_) in enumerate(zip(imgs, specs)):
+            img.copy_(inputs.bernoulli(s_["H"], s_["W"], 0.25 + 0.15 * ((rep + i) % 4), seed=rep * 31 + i,
+                                       device=DEV))
+        k.fill_(-1)
+        with torch.cuda.stream(side):
+            eager = ccl.label(other, 8)      # same stream, same workspace, between replays
+        torch.cuda.synchronize()
+        say(f"case captured replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        for i, img in enumerate(imgs):
+            ref, kref = _oracle(img, conns[i])
+            assert np.array_equal(outs[i].cpu().numpy(), ref), (rep, i)
+            assert int(k[i].item()) == kref, (rep, i)
+        assert np.array_equal(eager.cpu().numpy(), _oracle(other, 8)[0])
+    del g
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("slack", [0, -1])
+def test_serve_admission_is_exact(ccl, slack):
+    """A slot holding exactly the workspace of five mixed images (row pairs,
+    single rows, gray levels: three launch groups) takes all five as one
+    batch; one byte less and the fifth waits for the next batch."""
+    from paper_1606_05973_amd import serve
+    imgs = [inputs.bernoulli(300 + 40 * i, 700 - 30 * i, 0.5, seed=50 + i, device=DEV) for i in range(5)]
+    conns = [8, 4, 8, 8, 4]
+    scans = [0, 0, 1, 0, 0]
+    grays = [False, False, False, True, False]
+    need = ccl.batch_workspace_bytes([tuple(im.shape) for im in imgs], conns, 0, scans, grays)
+    srv = serve.Server(hbm_budget=need + slack, n_streams=1, max_batch=16)
+    blocker = torch.zeros((64, 64), dtype=torch.uint8, device=DEV)
+    gate = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(gate):
+        torch.cuda._sleep(500_000_000)   # the first batch waits on this stream (a fraction of a second)
+        first = srv.submit(blocker, 8)
+    time.sleep(0.005)                    # the scheduler has launched the blocker alone
+    reqs = [srv.submit(im, c, scan=sc, gray=g) for im, c, sc, g in zip(imgs, conns, scans, grays)]
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert first.done
+    assert st["batches"] == (2 if slack == 0 else 3), st
+    for im, c, g, r in zip(imgs, conns, grays, reqs):
+        host = im.cpu().numpy()
+        ref = oracle.gray(host, c)[0] if g else oracle.cclremsp(host, c)[0]
+        assert np.array_equal(r.labels.cpu().numpy(), ref)

@@ -205,6 +205,107 @@ def test_full_16384_grf(ccl):
     check(ccl, img, 8, what="16384^2 grf sigma 8")
 
 
+# The remaining densities of the single-image configuration, including the
+# 8-connectivity percolation threshold (p = 0.407) where a missing barrier in
+# the component-label kernel once showed as a few wrong pixels.
+@pytest.mark.parametrize("side,p,conn", [(21568, 0.1, 8), (21568, 0.3, 8), (21568, 0.407, 8), (21568, 0.9, 8),
+                                         (21568, 0.407, 4), (16384, 0.5, 8), (16384, 0.5, 4)])
+def test_full_size_bernoulli(ccl, side, p, conn):
+    img = inputs.bernoulli(side, side, p, seed=3, device=DEV)
+    check(ccl, img, conn, what=f"{side}^2 p={p}")
+
+
+@pytest.mark.parametrize("sigma", [2.0, 32.0])
+@pytest.mark.parametrize("q", [0.3, 0.7])
+def test_full_16384_grf_range(ccl, sigma, q):
+    img = inputs.grf(16384, 16384, sigma, q, seed=4, device=DEV)
+    for conn in (8, 4):
+        check(ccl, img, conn, what=f"16384^2 grf sigma={sigma} q={q}")
+
+
+@pytest.mark.parametrize("name", ["ones", "zeros", "hstripes", "vstripes"])
+def test_full_20000_constant_and_stripes(ccl, name):
+    """The longest cross-tile merge chains (one component over the whole
+    image) and the tallest / widest components, with their closed-form K."""
+    img = inputs.adversarial(name, 20000, 20000, device=DEV)
+    expect = {"ones": 1, "zeros": 0, "hstripes": 10000, "vstripes": 10000}[name]
+    for conn in (8, 4):
+        got, k = check(ccl, img, conn, what=f"20000^2 {name}")
+        assert k == expect
+        if name == "ones":
+            assert got.min() == 1 and got.max() == 1
+        if name == "hstripes":
+            assert got[::2, :].min() == 1 and got[-2, 0] == 10000 and not got[1::2, :].any()
+
+
+def test_plain_boundary_calls(ccl):
+    """ccl_label and ccl_label_batch called with exactly their contract
+    signatures (seven-field descriptors) on real images."""
+    import ctypes
+    lib = ccl._lib
+    imgs = [inputs.bernoulli(517, 1030, 0.45, seed=1, device=DEV),
+            inputs.grf(300, 257, 5.0, 0.5, seed=2, device=DEV),
+            inputs.adversarial("spiral", 199, 333, device=DEV),
+            inputs.bernoulli(64, 4096, 0.6, seed=3, device=DEV)]
+    conns = [8, 4, 8, 4]
+    for img, conn in zip(imgs, conns):
+        say(f"case ccl_label shape={tuple(img.shape)} conn={conn}")
+        out = torch.full(tuple(img.shape), -9, dtype=torch.int32, device=DEV)
+        H, W = img.shape
+        assert lib.ccl_label(img.data_ptr(), H, W, img.stride(0), conn, out.data_ptr(), None) == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.cclremsp(img.cpu().numpy(), conn)[0])
+    say("case ccl_label_batch plain descriptors")
+    outs = [torch.full(tuple(im.shape), -9, dtype=torch.int32, device=DEV) for im in imgs]
+    k = torch.full((len(imgs),), -1, dtype=torch.int32, device=DEV)
+    arr = (ccl.ImageDesc * len(imgs))()
+    for i, (img, conn) in enumerate(zip(imgs, conns)):
+        arr[i].img = img.data_ptr()
+        arr[i].H, arr[i].W = img.shape
+        arr[i].stride = img.stride(0)
+        arr[i].conn = conn
+        arr[i].labels = outs[i].data_ptr()
+        arr[i].num_components = k.data_ptr() + 4 * i if i != 2 else None
+    need = lib.ccl_workspace_bytes(517, 1030, 8)
+    assert need > 0 and lib.ccl_reserve(need, None) == 0
+    assert lib.ccl_label_batch(arr, len(imgs), None) == 0
+    torch.cuda.synchronize()
+    for i, (img, conn) in enumerate(zip(imgs, conns)):
+        ref, kref = oracle.cclremsp(img.cpu().numpy(), conn)
+        assert np.array_equal(outs[i].cpu().numpy(), ref), i
+        assert int(k[i].item()) == (kref if i != 2 else -1)
+    assert lib.ccl_strerror(0) == b"success"
+
+
+def test_binding_rejects_wrong_output_buffers(ccl):
+    img = inputs.bernoulli(40, 50, 0.5, seed=1, device=DEV)
+    good = torch.empty((40, 50), dtype=torch.int32, device=DEV)
+    bad_outs = [torch.empty((40, 51), dtype=torch.int32, device=DEV),
+                torch.empty((40, 50), dtype=torch.int64, device=DEV),
+                torch.empty((50, 40), dtype=torch.int32, device=DEV).t(),
+                torch.empty((40, 50), dtype=torch.int32)]
+    for bad in bad_outs:
+        with pytest.raises(ValueError):
+            ccl.label(img, 8, out=bad)
+        with pytest.raises(ValueError):
+            ccl.label(img, 8, out=bad, scan=ccl.SCAN_ROW)
+        with pytest.raises(ValueError):
+            ccl.label_batch([img, img], 8, outs=[good, bad])
+        with pytest.raises(ValueError):
+            ccl.BatchGraph([img, img], 8, outs=[good, bad])
+    short = torch.zeros(1, dtype=torch.int32, device=DEV)
+    with pytest.raises(ValueError):
+        ccl.label_batch([img, img], 8, num_components=short)
+    with pytest.raises(ValueError):
+        ccl.label_batch([img, img], 8, num_components=torch.zeros(4, dtype=torch.int32, device=DEV)[::2])
+    with pytest.raises(ValueError):
+        ccl.label(img, 8, num_components=torch.zeros(1, dtype=torch.int64, device=DEV))
+    with pytest.raises(ValueError):
+        ccl.label_batch([img, img], 8, outs=[good])
+    with pytest.raises(ValueError):
+        ccl.label_batch([img, img], [8])
+
+
 @pytest.mark.parametrize("name", ["spiral", "checkerboard", "comb", "diagonal"])
 def test_full_20000_adversarial(ccl, name):
     img = inputs.adversarial(name, 20000, 20000, device=DEV)
