@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--ablation-steps", type=int, default=5,
                     help="steps of the one-row vs two-row scan comparison (0 = skip)")
+    ap.add_argument("--order-steps", type=int, default=10,
+                    help="steps of the provisional-order (paper numbering) measurement (0 = skip)")
     ap.add_argument("--batch", type=int, default=256, help="images in the batched measurement (0 = skip)")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--serve-rates", default="1000,5000,10000,20000,50000,max",
@@ -436,6 +438,30 @@ def main():
         record["scan_ablation"] = {"pair_rows_ms": round(pair_ms, 4), "single_rows_ms": round(row_ms, 4),
                                    "pair_speedup": round(row_ms / pair_ms, 3)}
         log(f"scan ablation: pair {pair_ms:.3f} ms, row {row_ms:.3f} ms")
+    if args.order_steps > 0 and not gray and args.scan == "pair" and not level:
+        # the paper's own numbering (Algorithm 3's flatten over provisional
+        # labels): same image, consecutive labels in (tile, component) order
+        ccl.label_provisional(img, args.conn, out=out, tile=args.tile)
+        ccl.profile(True)
+        ccl.profile_read()
+        t_prov = _median_ms(torch, lambda: ccl.label_provisional(img, args.conn, out=out, tile=args.tile),
+                            args.order_steps)
+        ccl.profile(False)
+        pph, pn = ccl.profile_read()
+        rec_p = {"ms_per_step": round(t_prov, 4), "gpx_per_s": round(px / (t_prov * 1e-3) / 1e9, 2),
+                 "phase_ms": {k: round(v / max(pn, 1), 4) for k, v in pph.items()},
+                 "canonical_ms_per_step": round(ms_step, 4)}
+        if not args.no_verify:
+            import numpy as np
+
+            import oracle
+            th_, tw_ = ccl.tile_shape(args.tile, args.conn)
+            kp = torch.zeros(1, dtype=torch.int32, device=dev)
+            ccl.label_provisional(img, args.conn, out=out, tile=args.tile, num_components=kp)
+            pref, pk = oracle.provisional(img.cpu().numpy(), args.conn, th_, tw_, 2 if args.conn == 8 else 1)
+            rec_p["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), pref)) and int(kp.item()) == pk
+        record["provisional_order"] = rec_p
+        log(f"provisional order: {t_prov:.3f} ms")
     del out, img
     torch.cuda.empty_cache()
     ccl.release()

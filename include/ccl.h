@@ -51,7 +51,8 @@ typedef enum {
     CCL_ERR_SCAN = -12,     /* unknown scan strategy                            */
     CCL_ERR_BUDGET = -13,   /* request needs more workspace than a server slot  */
     CCL_ERR_TICKET = -14,   /* unknown server ticket                            */
-    CCL_ERR_GRAY = -15      /* gray flag other than 0 or 1                      */
+    CCL_ERR_GRAY = -15,     /* gray flag other than 0 or 1                      */
+    CCL_ERR_ORDER = -16     /* unknown output order                             */
 } ccl_status;
 
 /*
@@ -68,6 +69,24 @@ typedef enum {
  * Both give the same labels.
  */
 typedef enum { CCL_SCAN_PAIR = 0, CCL_SCAN_ROW = 1 } ccl_scan;
+
+/*
+ * Output numbering.
+ *   CCL_ORDER_CANONICAL    components numbered 1..K by their smallest raster
+ *                          index (the default; independent of tiling).
+ *   CCL_ORDER_PROVISIONAL  the flatten's numbering (Algorithm 3, Section III):
+ *                          1..K in the order of each set's smallest
+ *                          provisional label, the provisional labels being
+ *                          the tile-local components in (tile in raster
+ *                          order, component in the tile's node order) order,
+ *                          as PARemSP (Algorithm 7) numbers each thread's
+ *                          labels after those of the threads before it.  The
+ *                          partition into components is the same; only the
+ *                          numbers differ, and they depend on the tile shape.
+ *                          Skips the tile-local canonical keys and the
+ *                          per-row rank scan.
+ */
+typedef enum { CCL_ORDER_CANONICAL = 0, CCL_ORDER_PROVISIONAL = 1 } ccl_order;
 
 /*
  * ccl_label -- label one image (the whole two-pass method of Section III/IV:
@@ -182,8 +201,18 @@ int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, in
 int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
                    int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
 
+/*
+ * ccl_label_provisional -- as ccl_label_ex, numbering the components in
+ * provisional order (CCL_ORDER_PROVISIONAL): consecutive labels 1..K, as the
+ * paper's flatten hands them out.  K is the same as with ccl_label, and
+ * renumbering the output by smallest raster index gives ccl_label's output.
+ */
+int ccl_label_provisional(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
+                          int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
+
 /* One image of an extended batch.  The first seven fields are those of
- * ccl_image_desc; the options are as in ccl_label_level / ccl_label_gray. */
+ * ccl_image_desc; the options are as in ccl_label_level / ccl_label_gray /
+ * ccl_label_provisional.  All-zero options give ccl_label's labeling. */
 typedef struct {
     const uint8_t *img;      /* device */
     int64_t H, W, stride;
@@ -193,13 +222,18 @@ typedef struct {
     int level;               /* foreground iff byte > level; 0 = nonzero */
     int scan;                /* ccl_scan; 0 = CCL_SCAN_PAIR */
     int gray;                /* 1: gray-level labeling (see ccl_label_gray; scan is ignored) */
+    int order;               /* ccl_order; 0 = CCL_ORDER_CANONICAL */
+    int tile;                /* tile configuration id for this image; 0 = the call's tile */
 } ccl_image_desc_ex;
 
 /*
  * ccl_label_batch_ex -- ccl_label_batch over extended descriptors, with
- *   tile    tile configuration id used for every image (0 = each image's
- *           kind takes its default, ccl_tile_default).
- * Errors, capture and workspace as for ccl_label_batch.
+ *   tile    tile configuration id for the images whose descriptor names
+ *           none (0 = each image's kind takes its default, ccl_tile_default).
+ * Images are launched in groups of the same kind (row pairs, single rows,
+ * gray levels), output order and tile configuration: one launch per phase
+ * per group.  Errors, capture and workspace as for ccl_label_batch, plus
+ * CCL_ERR_TILE / CCL_ERR_ORDER for a descriptor's tile or order.
  */
 int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream);
 

@@ -22,6 +22,9 @@ label(img, conn, level)      -> labels                  the reference labeling (
 binarize(img, level)         -> uint8 0/1               Section V thresholding
 gray(img, conn)              -> (labels, K)             gray-level extension (Section V):
                                                         equal nonzero neighbours connect
+provisional(img, conn, tile_h, tile_w, block, gray)
+                             -> (labels, K)             the flatten's numbering (Algorithm 3)
+                                                        over tile-major provisional labels
 
 All labelings returned by ``cclremsp``, ``aremsp`` and ``paremsp`` use the
 canonical numbering: 0 is background and component k (1-based) is the k-th
@@ -78,6 +81,8 @@ def _load():
             lib.oracle_merger_pairs.restype = None
             lib.oracle_flatten.argtypes = [i32p, ctypes.c_int32]
             lib.oracle_flatten.restype = ctypes.c_int32
+            lib.oracle_provisional.argtypes = [i32p, i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+            lib.oracle_provisional.restype = i64
             _lib = lib
     return _lib
 
@@ -195,3 +200,26 @@ def label(img, conn: int = 8, level: int | None = None):
     if level is not None:
         img = binarize(img, level)
     return cclremsp(img, conn)[0]
+
+
+def provisional(img, conn: int, tile_h: int, tile_w: int, block: int = 1, gray_levels: bool = False):
+    """Labels numbered in provisional order, the numbering of the flatten
+    (Algorithm 3, Section III): label k goes to the set whose smallest
+    provisional label is the k-th smallest among the sets' smallest labels.
+
+    The provisional labels are those of a tiled two-pass scan: the image is
+    cut into tile_h x tile_w tiles, taken in raster order, each handing out
+    its labels after those of the tiles before it (the disjoint per-thread
+    label ranges of Algorithm 7, Section IV, with tiles for row chunks).
+    Inside a tile the labels follow the scan's nodes: runs of `block` image
+    rows (2: the two-row mask of Fig. 1b; 1: single rows; single rows of
+    equal bytes with ``gray_levels``), ordered by (block row, first column);
+    a tile-local component is labeled by its first node.  So the smallest
+    provisional label of a set is the minimum over its pixels of
+    (tile index, block row inside the tile, column inside the tile), which
+    is what is ranked here; the partition itself is the oracle's
+    (``cclremsp`` or ``gray``)."""
+    glab, K = (gray if gray_levels else cclremsp)(img, conn)
+    H, W = glab.shape
+    k = _load().oracle_provisional(_i32ptr(glab), H, W, K, int(tile_h), int(tile_w), int(block))
+    return glab, _check(k)

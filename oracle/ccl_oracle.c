@@ -536,6 +536,67 @@ int64_t oracle_paremsp(const uint8_t *img, int64_t H, int64_t W, int64_t stride,
 }
 
 /* Canonical renumbering of an arbitrary labeling (0 = background).         */
+/*
+ * Provisional order: the numbering of the flatten (Algorithm 3) when the
+ * provisional labels come from a tiled scan -- tiles of th x tw pixels in
+ * raster order, each handing out its labels after those of the tiles before
+ * it (Algorithm 7's per-partition label ranges, with tiles for row chunks),
+ * and inside a tile one label per tile-local component, given in the order of
+ * the component's first node, the nodes being runs of `block` rows ordered
+ * by (block row, first column).  The smallest provisional label of a set is
+ * then the minimum over its pixels of (tile index, block row inside the
+ * tile, column inside the tile); the flatten numbers the sets 1..K in the
+ * order of those minima.  `labels` holds any labeling 1..K of the partition
+ * (0 = background); it is renumbered in place.  Returns K, or -1.
+ */
+static const int64_t *g_first; /* qsort context: smallest key of each set */
+static int by_first(const void *a, const void *b)
+{
+    const int64_t x = g_first[*(const int32_t *)a], y = g_first[*(const int32_t *)b];
+    return (x > y) - (x < y);
+}
+
+int64_t oracle_provisional(int32_t *labels, int64_t H, int64_t W, int64_t K, int th, int tw, int block)
+{
+    if (!labels || H <= 0 || W <= 0 || K < 0 || th <= 0 || tw <= 0 || block <= 0 || th % block)
+        return -1;
+    int64_t *first = malloc(sizeof(int64_t) * (size_t)(K + 1));
+    int32_t *order = malloc(sizeof(int32_t) * (size_t)(K + 1));
+    int32_t *rank = malloc(sizeof(int32_t) * (size_t)(K + 1));
+    if (!first || !order || !rank) {
+        free(first);
+        free(order);
+        free(rank);
+        return -1;
+    }
+    const int64_t ntx = (W + tw - 1) / tw;
+    for (int64_t k = 0; k <= K; k++)
+        first[k] = INT64_MAX;
+    for (int64_t r = 0; r < H; r++)
+        for (int64_t c = 0; c < W; c++) {
+            const int32_t g = labels[r * W + c];
+            if (g <= 0)
+                continue;
+            const int64_t tile = (r / th) * ntx + c / tw;
+            const int64_t key = tile * (int64_t)th * tw + ((r % th) / block) * tw + c % tw;
+            if (key < first[g])
+                first[g] = key;
+        }
+    for (int64_t k = 0; k < K; k++)
+        order[k] = (int32_t)(k + 1);
+    g_first = first;
+    qsort(order, (size_t)K, sizeof(int32_t), by_first);
+    for (int64_t k = 0; k < K; k++)
+        rank[order[k]] = (int32_t)(k + 1);
+    for (int64_t i = 0; i < H * W; i++)
+        if (labels[i] > 0)
+            labels[i] = rank[labels[i]];
+    free(first);
+    free(order);
+    free(rank);
+    return K;
+}
+
 int64_t oracle_canonical(int32_t *labels, int64_t H, int64_t W)
 {
     int32_t maxlabel = 0;

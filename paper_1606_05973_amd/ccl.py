@@ -35,7 +35,8 @@ class ImageDescEx(ctypes.Structure):
     """ccl_image_desc_ex of include/ccl.h (the extended calls)."""
     _fields_ = [("img", ctypes.c_void_p), ("H", _i64), ("W", _i64), ("stride", _i64),
                 ("conn", ctypes.c_int), ("labels", ctypes.c_void_p), ("num_components", ctypes.c_void_p),
-                ("level", ctypes.c_int), ("scan", ctypes.c_int), ("gray", ctypes.c_int)]
+                ("level", ctypes.c_int), ("scan", ctypes.c_int), ("gray", ctypes.c_int),
+                ("order", ctypes.c_int), ("tile", ctypes.c_int)]
 
 
 _lib.ccl_label.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _stream]
@@ -48,6 +49,8 @@ _lib.ccl_label_level.restype = ctypes.c_int
 _lib.ccl_label_gray.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
                                 _stream]
 _lib.ccl_label_gray.restype = ctypes.c_int
+_lib.ccl_label_provisional.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _i32p, ctypes.c_int, _stream]
+_lib.ccl_label_provisional.restype = ctypes.c_int
 _lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, _stream]
 _lib.ccl_label_batch.restype = ctypes.c_int
 _lib.ccl_label_batch_ex.argtypes = [ctypes.POINTER(ImageDescEx), ctypes.c_int, ctypes.c_int, _stream]
@@ -113,9 +116,10 @@ STATUS = {
     "CCL_ERR_NULL": -1, "CCL_ERR_SHAPE": -2, "CCL_ERR_STRIDE": -3, "CCL_ERR_CONN": -4,
     "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
     "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11, "CCL_ERR_SCAN": -12,
-    "CCL_ERR_BUDGET": -13, "CCL_ERR_TICKET": -14, "CCL_ERR_GRAY": -15,
+    "CCL_ERR_BUDGET": -13, "CCL_ERR_TICKET": -14, "CCL_ERR_GRAY": -15, "CCL_ERR_ORDER": -16,
 }
 SCAN_PAIR, SCAN_ROW = 0, 1   # ccl_scan: two-row (default) / one-row tile-local scan
+CANONICAL, PROVISIONAL = 0, 1   # ccl_order: smallest raster index (default) / the flatten's provisional order
 
 
 class CCLError(RuntimeError):
@@ -213,6 +217,22 @@ def label(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, til
     return out
 
 
+def label_provisional(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
+                      num_components: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Labels numbered 1..K in provisional order (ccl_label_provisional): the
+    same components as label(), numbered as the paper's flatten numbers them
+    (by each set's smallest provisional label: tile, then component)."""
+    H, W, stride = _img_geometry(img)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    _check_out(out, img)
+    _check_counts(num_components, 1, img.device)
+    nc = num_components.data_ptr() if num_components is not None else None
+    _check(_lib.ccl_label_provisional(img.data_ptr(), H, W, stride, int(conn), out.data_ptr(), nc, int(tile),
+                                      _stream_handle(stream)))
+    return out
+
+
 def label_gray(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, tile: int = 0,
                num_components: torch.Tensor | None = None, stream=None, level: int = 0) -> torch.Tensor:
     """Gray-level labeling: object pixels are bytes > `level`; neighbouring
@@ -233,7 +253,7 @@ def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: 
     return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
 
 
-def _descs(imgs, conns, outs, num_components, levels=None, scans=None, grays=None):
+def _descs(imgs, conns, outs, num_components, levels=None, scans=None, grays=None, orders=None, tiles=None):
     """Extended descriptors of a batch, after checking every buffer the
     library will write: outs[i] for image i, slot i of num_components."""
     n = len(imgs)
@@ -255,6 +275,8 @@ def _descs(imgs, conns, outs, num_components, levels=None, scans=None, grays=Non
         arr[i].level = int(levels[i]) if levels is not None else 0
         arr[i].scan = int(scans[i]) if scans is not None else 0
         arr[i].gray = int(bool(grays[i])) if grays is not None else 0
+        arr[i].order = int(orders[i]) if orders is not None else 0
+        arr[i].tile = int(tiles[i]) if tiles is not None else 0
     return arr
 
 
@@ -266,18 +288,21 @@ def _per_image(v, n):
 
 
 def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
-                stream=None, level=0, scan=SCAN_PAIR, gray=False):
-    """Label a list of images with one launch per phase for the whole batch
+                stream=None, level=0, scan=SCAN_PAIR, gray=False, order=CANONICAL, tiles=0):
+    """Label a list of images with one launch per phase and launch group
     (ccl_label_batch_ex).
 
-    conn, level, scan, gray: one value or a per-image list.  num_components:
-    optional contiguous device int32 tensor with one slot per image."""
+    conn, level, scan, gray, order: one value or a per-image list.  tiles:
+    per-image tile ids (0 = `tile`, whose 0 means each kind's default).
+    num_components: optional contiguous device int32 tensor with one slot per
+    image."""
     n = len(imgs)
     conns, levels = _per_image(conn, n), _per_image(level, n)
     scans, grays = _per_image(scan, n), _per_image(gray, n)
+    orders, tl = _per_image(order, n), _per_image(tiles, n)
     if outs is None:
         outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
-    arr = _descs(imgs, conns, outs, num_components, levels, scans, grays)
+    arr = _descs(imgs, conns, outs, num_components, levels, scans, grays, orders, tl)
     _check(_lib.ccl_label_batch_ex(arr, n, int(tile), _stream_handle(stream)))
     return outs
 
@@ -305,13 +330,14 @@ class BatchGraph:
     reused on every replay."""
 
     def __init__(self, imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Tensor | None = None,
-                 level=0, scan=SCAN_PAIR):
+                 level=0, scan=SCAN_PAIR, gray=False, order=CANONICAL, tiles=0):
         n = len(imgs)
         conns, levels, scans = _per_image(conn, n), _per_image(level, n), _per_image(scan, n)
+        grays, orders, tl = _per_image(gray, n), _per_image(order, n), _per_image(tiles, n)
         if outs is None:
             outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
         self.imgs, self.outs, self.counts = list(imgs), outs, num_components
-        arr = _descs(imgs, conns, outs, num_components, levels, scans)
+        arr = _descs(imgs, conns, outs, num_components, levels, scans, grays, orders, tl)
         h = ctypes.c_void_p()
         _check(_lib.ccl_batch_graph_create(arr, n, int(tile), ctypes.byref(h)))
         self._h = h
@@ -340,9 +366,11 @@ def workspace_bytes(H: int, W: int, conn: int = 8, tile: int = 0, scan: int = SC
     return int(_lib.ccl_workspace_bytes(H, W, conn))
 
 
-def batch_workspace_bytes(shapes, conn=8, tile: int = 0, scan=SCAN_PAIR, gray=False) -> int:
+def batch_workspace_bytes(shapes, conn=8, tile: int = 0, scan=SCAN_PAIR, gray=False, order=CANONICAL,
+                          tiles=0) -> int:
     n = len(shapes)
     conns, scans, grays = _per_image(conn, n), _per_image(scan, n), _per_image(gray, n)
+    orders, tl = _per_image(order, n), _per_image(tiles, n)
     arr = (ImageDescEx * max(n, 1))()
     for i, (H, W) in enumerate(shapes):
         arr[i].img = 1
@@ -351,6 +379,8 @@ def batch_workspace_bytes(shapes, conn=8, tile: int = 0, scan=SCAN_PAIR, gray=Fa
         arr[i].conn = int(conns[i])
         arr[i].scan = int(scans[i])
         arr[i].gray = int(bool(grays[i]))
+        arr[i].order = int(orders[i])
+        arr[i].tile = int(tl[i])
     return int(_lib.ccl_batch_workspace_bytes(arr, n, int(tile)))
 
 

@@ -26,11 +26,11 @@ typedef ccl_image_desc_ex Desc;
 
 // ---------------------------------------------------------------- tiles
 // A tile configuration is (block rows, width).  The tile height is block
-// rows x 2 under 8-connectivity (two image rows per block row) and block
-// rows x 1 under 4-connectivity.  id 1 is the default.
+// rows x 2 under 8-connectivity with the row-pair scan (two image rows per
+// block row), block rows x 1 with single rows, block rows / 2 for gray
+// levels.
 struct TileCfg {
     int nsr, tw;
-    bool dflt;   // asked for id 0: each launch group takes its own default
 };
 constexpr TileCfg kTiles[] = {{32, 256}, {16, 256}, {16, 512}, {64, 128}, {32, 128}, {8, 512}, {64, 256}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
@@ -38,32 +38,51 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 // Image rows per block row: two under 8-connectivity with the pair-row scan
 // (the default), one otherwise.
 inline int bh_of(int conn, int scan) { return (conn == 8 && scan == CCL_SCAN_PAIR) ? 2 : 1; }
-inline int bh_of(const Desc &d) { return d.gray ? 1 : bh_of(d.conn, d.scan); }
 
-// Launch groups of a batch: row-pair runs, single-row runs, gray levels.
-enum Group { kPair = 0, kRow = 1, kGray = 2, kGroups = 3 };
-inline int group_of(const Desc &d) { return d.gray ? kGray : (bh_of(d) == 2 ? kPair : kRow); }
-inline int group_of(int conn, int scan, int gray) { return gray ? kGray : (bh_of(conn, scan) == 2 ? kPair : kRow); }
+// Kinds of image, each with kernels of its own: row-pair runs, single-row
+// runs, gray levels.
+enum Kind { kPair = 0, kRow = 1, kGray = 2, kKinds = 3 };
+inline int kind_of(int conn, int scan, int gray) { return gray ? kGray : (bh_of(conn, scan) == 2 ? kPair : kRow); }
+inline int kind_of(const Desc &d) { return kind_of(d.conn, d.scan, d.gray); }
 
-// Default tile id per group (fastest in a sweep of the configurations on
+// Default tile id per kind (fastest in a sweep of the configurations on
 // 21568^2 images): row pairs 64x256 pixels, single rows 64x128, gray levels
 // 32x256.
-constexpr int kDefaultTile[kGroups] = {1, 4, 7};
-inline TileCfg tile_for(const TileCfg &c, int group) { return c.dflt ? kTiles[kDefaultTile[group] - 1] : c; }
+constexpr int kDefaultTile[kKinds] = {1, 4, 7};
+
+// Tile configuration id (1-based) an image runs with: its descriptor's, else
+// the call's, else its kind's default.
+inline int tile_id_of(const Desc &d, int call_tile) {
+    const int t = d.tile ? d.tile : call_tile;
+    return t ? t : kDefaultTile[kind_of(d)];
+}
+
+// Images of one kind, output order and tile configuration share every
+// launch of a batch (one launch group).
+struct GroupKey {
+    int kind, order, tile;
+    bool operator<(const GroupKey &o) const {
+        return kind != o.kind ? kind < o.kind : (order != o.order ? order < o.order : tile < o.tile);
+    }
+};
+inline GroupKey key_of(const Desc &d, int call_tile) { return {kind_of(d), d.order, tile_id_of(d, call_tile)}; }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
-    int32_t th, NTY, NTX, NT, nblk, nedge, nm, rcap, rw, cap, hep, vep;
+    int32_t th, NTY, NTX, NT, nblk, nseg, nedge, nm, rcap, rw, cap, hep, vep;
     size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
-// bh: image rows per block row; gray-level tiles hold half the rows (one
-// per block row) so that every pixel can be a node.
-Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c, bool gray = false) {
+Layout layout_of(const Desc &d, const GroupKey &g) {
+    const TileCfg &c = kTiles[g.tile - 1];
+    const int64_t H = d.H, W = d.W;
+    const bool gray = g.kind == kGray;
     Layout L{};
-    L.th = gray ? c.nsr / 2 : c.nsr * bh;
+    // gray-level tiles hold half the rows (one per block row) so that every
+    // pixel can be a node
+    L.th = gray ? c.nsr / 2 : c.nsr * (g.kind == kPair ? 2 : 1);
     L.NTY = (int32_t)((H + L.th - 1) / L.th);
     L.NTX = (int32_t)((W + c.tw - 1) / c.tw);
     L.NT = L.NTY * L.NTX;
@@ -71,7 +90,10 @@ Layout layout_of(int64_t H, int64_t W, int bh, const TileCfg &c, bool gray = fal
     L.rcap = c.nsr * (c.tw / 2);
     L.rw = L.rcap / 32;
     L.cap = 2 * (L.th + c.tw);
-    const int64_t nseg = H * (int64_t)L.NTX;
+    // the rank scan runs over (row, tile column) segments, or over tiles in
+    // provisional order
+    const int64_t nseg = g.order == CCL_ORDER_PROVISIONAL ? (int64_t)L.NT : H * (int64_t)L.NTX;
+    L.nseg = (int32_t)nseg;
     L.nblk = (int32_t)((nseg + kScanChunk - 1) / kScanChunk);
     L.nedge = (int32_t)((L.NTY - 1) * ((W + 31) / 32) + (L.NTX - 1) * ((H + 31) / 32));
     const size_t NT = (size_t)L.NT;
@@ -117,30 +139,35 @@ int check_image(const void *img, int64_t H, int64_t W, int64_t stride, int conn,
 
 int check_level(int level) { return (level < 0 || level > 255) ? CCL_ERR_LEVEL : CCL_OK; }
 
+int check_tile(int tile) { return (tile < 0 || tile > kNumTiles) ? CCL_ERR_TILE : CCL_OK; }
+
 int check_opts(const Desc &d) {
     if (d.scan != CCL_SCAN_PAIR && d.scan != CCL_SCAN_ROW)
         return CCL_ERR_SCAN;
     if (d.gray != 0 && d.gray != 1)
         return CCL_ERR_GRAY;
-    return check_level(d.level);
+    if (d.order != CCL_ORDER_CANONICAL && d.order != CCL_ORDER_PROVISIONAL)
+        return CCL_ERR_ORDER;
+    int st = check_tile(d.tile);
+    return st != CCL_OK ? st : check_level(d.level);
 }
 
-int resolve_tile(int tile, TileCfg *out) {
-    if (tile == 0) {
-        *out = kTiles[0];
-        out->dflt = true;
-        return CCL_OK;
-    }
-    if (tile < 1 || tile > kNumTiles)
-        return CCL_ERR_TILE;
-    *out = kTiles[tile - 1];
-    return CCL_OK;
+int check_desc(const Desc &d) {
+    const int st = check_image(d.img, d.H, d.W, d.stride, d.conn, d.labels);
+    return st != CCL_OK ? st : check_opts(d);
 }
 
 // ------------------------------------------------------------- workspace
+// Per (device, stream): the device workspace, and two pinned host buffers
+// that stage batch tables (a copy from pinned memory is asynchronous; each
+// buffer is rewritten only once its previous copy has run).
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
+    char *stage[2] = {nullptr, nullptr};
+    size_t stage_bytes[2] = {0, 0};
+    hipEvent_t stage_done[2] = {nullptr, nullptr};
+    int next_stage = 0;
 };
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
@@ -175,6 +202,47 @@ int get_workspace(hipStream_t stream, size_t need, void **out) {
     }
     *out = w.ptr;
     return CCL_OK;
+}
+
+// A pinned staging buffer of at least `need` bytes for a table copy on
+// `stream` (not capturing), and the event to record after that copy.
+int get_stage(hipStream_t stream, size_t need, char **out, hipEvent_t *done) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return CCL_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace &w = g_ws[{dev, stream}];
+    const int i = w.next_stage;
+    w.next_stage ^= 1;
+    if (w.stage_done[i] && hipEventSynchronize(w.stage_done[i]) != hipSuccess)
+        return CCL_ERR_HIP;
+    if (!w.stage_done[i] && hipEventCreateWithFlags(&w.stage_done[i], hipEventDisableTiming) != hipSuccess)
+        return CCL_ERR_HIP;
+    if (w.stage_bytes[i] < need) {
+        if (w.stage[i])
+            (void)hipHostFree(w.stage[i]);
+        w.stage[i] = nullptr;
+        w.stage_bytes[i] = 0;
+        const size_t grow = std::max(need, (size_t)64 << 10);
+        if (hipHostMalloc(reinterpret_cast<void **>(&w.stage[i]), grow) != hipSuccess) {
+            (void)hipGetLastError();
+            return CCL_ERR_NOMEM;
+        }
+        w.stage_bytes[i] = grow;
+    }
+    *out = w.stage[i];
+    *done = w.stage_done[i];
+    return CCL_OK;
+}
+
+void free_workspace(Workspace &w) {
+    (void)hipFree(w.ptr);
+    for (int i = 0; i < 2; i++) {
+        if (w.stage[i])
+            (void)hipHostFree(w.stage[i]);
+        if (w.stage_done[i])
+            (void)hipEventDestroy(w.stage_done[i]);
+    }
 }
 
 // Sets a pointer field of an Img (whose device view is in the global
@@ -213,6 +281,7 @@ Img make_img(const Desc &d, const Layout &L, char *base) {
     im.hep = L.hep;
     im.vep = L.vep;
     im.nblk = L.nblk;
+    im.nseg = L.nseg;
     return im;
 }
 
@@ -284,28 +353,33 @@ int persistent_groups(int threads) {
     return n;
 }
 
-template <int NSR, int TW, int BH>
+template <int NSR, int TW, int BH, int ORD>
 int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg, hipStream_t s) {
     if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
         return CCL_ERR_TOO_LARGE;
     const dim3 blk(kThreads);
+    const dim3 tile_groups((uint32_t)((tiles + kWaves - 1) / kWaves));
     PhaseMarks pm(s);
     pm.mark();
-    hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
+    hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH, ORD>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     pm.mark();
     if (edges > 0)
         hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((merge_split(BH) * edges + kThreads - 1) / kThreads)),
                            blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), dim3((uint32_t)((tiles + kWaves - 1) / kWaves)), blk, 0, s, b,
-                       (int32_t)tiles);
+    if (ORD == kCanonical)
+        hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), tile_groups, blk, 0, s, b, (int32_t)tiles);
+    else
+        hipLaunchKernelGGL((k_flatten_prov<NSR, TW, BH>), tile_groups, blk, 0, s, b, (int32_t)tiles);
     pm.mark();
     hipLaunchKernelGGL(k_scan_blocks, dim3((uint32_t)blocks), blk, 0, s, b);
     pm.mark();
     hipLaunchKernelGGL(k_scan_top, dim3((uint32_t)nimg), blk, 0, s, b);
     pm.mark();
-    hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), dim3((uint32_t)((tiles + kWaves - 1) / kWaves)), blk, 0, s,
-                       b, (int32_t)tiles);
+    if (ORD == kCanonical)
+        hipLaunchKernelGGL((k_comp_labels<NSR, TW, BH>), tile_groups, blk, 0, s, b, (int32_t)tiles);
+    else
+        hipLaunchKernelGGL((k_comp_labels_prov<NSR, TW, BH>), tile_groups, blk, 0, s, b, (int32_t)tiles);
     pm.mark();
 #define CCL_RELABEL(F_)                                                                                     \
     hipLaunchKernelGGL((k_relabel<NSR, TW, BH, F_>),                                                        \
@@ -322,13 +396,15 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
 
-int dispatch(const TileCfg &c, int group, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
+int dispatch(const GroupKey &g, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
              hipStream_t s) {
-#define CCL_TILE_CASE(N_, W_)                                                            \
-    if (c.nsr == N_ && c.tw == W_)                                                       \
-        return group == kPair ? launch_all<N_, W_, 2>(b, tiles, edges, blocks, nimg, s) \
-             : group == kRow  ? launch_all<N_, W_, 1>(b, tiles, edges, blocks, nimg, s) \
-                              : launch_all<N_, W_, 0>(b, tiles, edges, blocks, nimg, s);
+    const TileCfg &c = kTiles[g.tile - 1];
+#define CCL_ORD(N_, W_, B_) \
+    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, edges, blocks, nimg, s) \
+                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, edges, blocks, nimg, s))
+#define CCL_TILE_CASE(N_, W_)                                                                       \
+    if (c.nsr == N_ && c.tw == W_)                                                                  \
+        return g.kind == kPair ? CCL_ORD(N_, W_, 2) : g.kind == kRow ? CCL_ORD(N_, W_, 1) : CCL_ORD(N_, W_, 0);
     CCL_TILE_CASE(32, 256)
     CCL_TILE_CASE(16, 256)
     CCL_TILE_CASE(16, 512)
@@ -337,69 +413,88 @@ int dispatch(const TileCfg &c, int group, const Batch &b, int64_t tiles, int64_t
     CCL_TILE_CASE(8, 512)
     CCL_TILE_CASE(64, 256)
 #undef CCL_TILE_CASE
+#undef CCL_ORD
     return CCL_ERR_TILE;
 }
 
-// Images with the same rows per block row share every launch; a batch
-// mixing them runs as two such groups, one after the other on the stream.
+// ------------------------------------------------------------- batches
 // Table of a group of n images: n Img entries, then the n tile0, n edge0
 // and n scan0 keys as a compact array (searched by find_img).
 size_t group_table_bytes(size_t n) { return align_up(n * (sizeof(Img) + 3 * sizeof(int32_t))); }
 
-// Fills a group's table (Img entries and keys) in `tab`; returns the counts.
-int build_group_table(const Desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
-                      const std::vector<size_t> &offs, char *base, char *tab_bytes, int64_t *tiles_out,
-                      int64_t *edges_out, int64_t *blocks_out) {
+// The most table bytes a batch of n images can need (every image a group of
+// its own at worst).
+size_t max_tables_bytes(size_t n) { return n * group_table_bytes(1); }
+static_assert(sizeof(Img) + 3 * sizeof(int32_t) <= 256, "a group's table takes at most 256 bytes per image");
+
+// The layout of a batch's workspace: the tables of its launch groups (in
+// key order), then one region per image.
+struct Plan {
+    std::vector<GroupKey> keys;
+    std::vector<std::vector<int>> members;
+    std::vector<size_t> tab_at;       // table offset of each group
+    std::vector<Layout> lays;         // per image
+    std::vector<size_t> offs;         // region offset of each image
+    size_t tables = 0, bytes = 0;
+    bool upload = false;              // some group has more than one image (needs its table on the device)
+};
+
+Plan plan_batch(const Desc *descs, int n, int call_tile) {
+    Plan P;
+    std::map<GroupKey, std::vector<int>> by;
+    for (int i = 0; i < n; i++)
+        by[key_of(descs[i], call_tile)].push_back(i);
+    for (auto &kv : by) {
+        P.keys.push_back(kv.first);
+        P.tab_at.push_back(P.tables);
+        P.tables += group_table_bytes(kv.second.size());
+        P.upload |= kv.second.size() > 1;
+        P.members.push_back(std::move(kv.second));
+    }
+    size_t off = P.tables;
+    P.lays.resize(n);
+    P.offs.resize(n);
+    for (int i = 0; i < n; i++) {
+        P.lays[i] = layout_of(descs[i], key_of(descs[i], call_tile));
+        P.offs[i] = off;
+        off += P.lays[i].bytes;
+    }
+    P.bytes = off;
+    return P;
+}
+
+size_t batch_bytes(const Desc *descs, int n, int call_tile) { return plan_batch(descs, n, call_tile).bytes; }
+
+// One group's launch arguments, its table written to `tab_bytes` (host).
+struct GroupRun {
+    Batch b;
+    int64_t tiles, edges, blocks;
+};
+
+int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *tab_bytes, GroupRun *out) {
+    const std::vector<int> &idx = P.members[g];
     const int n = (int)idx.size();
     Img *tab = reinterpret_cast<Img *>(tab_bytes);
     int32_t *keys = reinterpret_cast<int32_t *>(tab_bytes + (size_t)n * sizeof(Img));
     int64_t tiles = 0, edges = 0, blocks = 0;
+    Batch b{};
+    b.n = n;
+    b.store = kStore16;
     for (int k = 0; k < n; k++) {
         const int i = idx[k];
-        tab[k] = make_img(descs[i], lays[i], base + offs[i]);
+        const Desc &d = descs[i];
+        tab[k] = make_img(d, P.lays[i], base + P.offs[i]);
         tab[k].tile0 = (int32_t)tiles;
         tab[k].edge0 = (int32_t)edges;
         tab[k].scan0 = (int32_t)blocks;
         keys[k] = tab[k].tile0;
         keys[n + k] = tab[k].edge0;
         keys[2 * n + k] = tab[k].scan0;
-        tiles += lays[i].NT;
-        edges += lays[i].nedge;
-        blocks += lays[i].nblk;
+        tiles += P.lays[i].NT;
+        edges += P.lays[i].nedge;
+        blocks += P.lays[i].nblk;
         if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
             return CCL_ERR_TOO_LARGE;
-    }
-    *tiles_out = tiles;
-    *edges_out = edges;
-    *blocks_out = blocks;
-    return CCL_OK;
-}
-
-// Workspace: [tables of the groups][per-image regions].  The group's table
-// is built in `htab` (pinned host memory that stays untouched until the
-// stream has passed the copy) or else in a temporary: a copy from pageable
-// memory has read it by the time the call returns, and on a stream being
-// captured the table is stored by k_put_words launches that carry it in
-// their arguments (a copy node would keep a pointer to the temporary).
-int run_group(const Desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
-              const std::vector<size_t> &offs, char *base, char *dtab, int group, const TileCfg &c,
-              hipStream_t stream, bool table_ready = false, char *htab = nullptr) {
-    const int n = (int)idx.size();
-    if (n == 0)
-        return CCL_OK;
-    const size_t tbytes = group_table_bytes((size_t)n);
-    std::vector<char> local(htab ? 0 : tbytes);
-    char *tab_bytes = htab ? htab : local.data();
-    const Img *tab = reinterpret_cast<const Img *>(tab_bytes);
-    int64_t tiles = 0, edges = 0, blocks = 0;
-    int st = build_group_table(descs, idx, lays, offs, base, tab_bytes, &tiles, &edges, &blocks);
-    if (st != CCL_OK)
-        return st;
-    Batch b{};
-    b.n = n;
-    b.store = kStore16;
-    for (int k = 0; k < n; k++) {
-        const Desc &d = descs[idx[k]];
         if (d.W > kVecMaxW)
             b.store = kStoreAny;
         else if (b.store == kStore16 && (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0))
@@ -407,102 +502,100 @@ int run_group(const Desc *descs, const std::vector<int> &idx, const std::vector<
     }
     if (n == 1) {
         b.one = tab[0];
-        b.tab = nullptr;
-        b.keys = nullptr;
     } else {
-        if (!table_ready) {
-            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-            if (hipStreamIsCapturing(stream, &cs) != hipSuccess)
-                return CCL_ERR_HIP;
-            if (cs == hipStreamCaptureStatusNone) {
-                if (hipMemcpyAsync(dtab, tab_bytes, tbytes, hipMemcpyHostToDevice, stream) != hipSuccess)
-                    return CCL_ERR_HIP;
-            } else {
-                static_assert(sizeof(WordChunk) == 4 * kChunkWords, "chunk layout");
-                const size_t words = tbytes / 4;   // tbytes is a multiple of 256
-                for (size_t at = 0; at < words; at += kChunkWords) {
-                    WordChunk ch;
-                    const int cnt = (int)std::min<size_t>(kChunkWords, words - at);
-                    memcpy(ch.w, tab_bytes + 4 * at, 4 * (size_t)cnt);
-                    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(kChunkWords), 0, stream,
-                                       reinterpret_cast<uint32_t *>(dtab) + at, cnt, ch);
-                }
-                if (hipGetLastError() != hipSuccess)
-                    return CCL_ERR_HIP;
-            }
-        }
-        b.tab = reinterpret_cast<const Img *>(dtab);
-        b.keys = reinterpret_cast<const int32_t *>(dtab + (size_t)n * sizeof(Img));
+        b.tab = reinterpret_cast<const Img *>(base + P.tab_at[g]);
+        b.keys = reinterpret_cast<const int32_t *>(base + P.tab_at[g] + (size_t)n * sizeof(Img));
     }
-    return dispatch(tile_for(c, group), group, b, tiles, edges, blocks, n, stream);
+    out->b = b;
+    out->tiles = tiles;
+    out->edges = edges;
+    out->blocks = blocks;
+    return CCL_OK;
 }
 
-// The group tables at the start of a batch's workspace.
-size_t tables_bytes(const size_t per_group[kGroups]) {
-    size_t off = 0;
-    for (int k = 0; k < kGroups; k++)
-        off += group_table_bytes(per_group[k]);
-    return off;
-}
-
-size_t batch_bytes(const Desc *descs, int n, const TileCfg &c, std::vector<Layout> *lays,
-                   std::vector<size_t> *offs) {
-    size_t per_group[kGroups] = {0, 0, 0};
-    for (int i = 0; i < n; i++)
-        per_group[group_of(descs[i])]++;
-    size_t off = tables_bytes(per_group);
-    for (int i = 0; i < n; i++) {
-        Layout L = layout_of(descs[i].H, descs[i].W, bh_of(descs[i]), tile_for(c, group_of(descs[i])),
-                             descs[i].gray != 0);
-        if (lays)
-            lays->push_back(L);
-        if (offs)
-            offs->push_back(off);
-        off += L.bytes;
-    }
-    return off;
-}
-
-// Launch a batch into a workspace of at least batch_bytes(descs) bytes.
-int run_batch_in(const Desc *descs, int n, const TileCfg &c, hipStream_t stream, char *base,
-                 char *htab = nullptr) {
-    std::vector<Layout> lays;
-    std::vector<size_t> offs;
-    batch_bytes(descs, n, c, &lays, &offs);
-    std::vector<int> g[kGroups];
-    for (int i = 0; i < n; i++)
-        g[group_of(descs[i])].push_back(i);
-    size_t at = 0;
-    for (int k = 0; k < kGroups; k++) {
-        const int st = run_group(descs, g[k], lays, offs, base, base + at, k, c, stream, false,
-                                 htab ? htab + at : nullptr);
+// Builds every group's table into `host` (P.tables bytes, laid out as the
+// start of the workspace) and the launch arguments.
+int build_plan(const Desc *descs, const Plan &P, char *base, char *host, std::vector<GroupRun> *runs) {
+    runs->resize(P.keys.size());
+    for (size_t g = 0; g < P.keys.size(); g++) {
+        const int st = build_group(descs, P, g, base, host + P.tab_at[g], &(*runs)[g]);
         if (st != CCL_OK)
             return st;
-        at += group_table_bytes(g[k].size());
     }
     return CCL_OK;
 }
 
-int run_batch(const Desc *descs, int n, const TileCfg &c, hipStream_t stream) {
-    void *ws = nullptr;
-    int st = get_workspace(stream, batch_bytes(descs, n, c, nullptr, nullptr), &ws);
-    if (st != CCL_OK)
-        return st;
-    return run_batch_in(descs, n, c, stream, static_cast<char *>(ws));
+int launch_plan(const Plan &P, const std::vector<GroupRun> &runs, hipStream_t stream) {
+    for (size_t g = 0; g < P.keys.size(); g++) {
+        const int st = dispatch(P.keys[g], runs[g].b, runs[g].tiles, runs[g].edges, runs[g].blocks,
+                                (int)P.members[g].size(), stream);
+        if (st != CCL_OK)
+            return st;
+    }
+    return CCL_OK;
 }
 
-// Device table of one group, uploaded synchronously (used before capture).
-int upload_group_table(const Desc *descs, const std::vector<int> &idx, const std::vector<Layout> &lays,
-                       const std::vector<size_t> &offs, char *base, char *dtab) {
-    const int n = (int)idx.size();
-    if (n <= 1)
-        return CCL_OK;
-    std::vector<char> tab(group_table_bytes((size_t)n));
-    int64_t tiles = 0, edges = 0, blocks = 0;
-    const int st = build_group_table(descs, idx, lays, offs, base, tab.data(), &tiles, &edges, &blocks);
+// The tables of a stream being captured: stored by k_put_words launches that
+// carry them in their arguments, so that every replay writes them again
+// (a copy node would keep a pointer to host memory that does not outlive
+// the call).
+int put_tables_captured(char *dst, const char *host, size_t bytes, hipStream_t stream) {
+    static_assert(sizeof(WordChunk) == 4 * kChunkWords, "chunk layout");
+    const size_t words = bytes / 4;   // table sizes are multiples of 256
+    for (size_t at = 0; at < words; at += kChunkWords) {
+        WordChunk ch;
+        const int cnt = (int)std::min<size_t>(kChunkWords, words - at);
+        memcpy(ch.w, host + 4 * at, 4 * (size_t)cnt);
+        hipLaunchKernelGGL(k_put_words, dim3(1), dim3(kChunkWords), 0, stream, reinterpret_cast<uint32_t *>(dst) + at,
+                           cnt, ch);
+    }
+    return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
+}
+
+// Launch a batch into a workspace of at least P.bytes bytes.  The tables go
+// through `htab` (pinned host memory of at least P.tables bytes that stays
+// untouched until the stream has passed the copy) when given, else through
+// the stream's staging buffers, or kernel arguments while capturing.
+int run_plan_in(const Desc *descs, const Plan &P, hipStream_t stream, char *base, char *htab = nullptr) {
+    std::vector<GroupRun> runs;
+    if (!P.upload) {
+        std::vector<char> local(P.tables);
+        const int st = build_plan(descs, P, base, local.data(), &runs);
+        return st != CCL_OK ? st : launch_plan(P, runs, stream);
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess)
+        return CCL_ERR_HIP;
+    if (cs != hipStreamCaptureStatusNone) {
+        std::vector<char> local(P.tables);
+        int st = build_plan(descs, P, base, local.data(), &runs);
+        if (st == CCL_OK)
+            st = put_tables_captured(base, local.data(), P.tables, stream);
+        return st != CCL_OK ? st : launch_plan(P, runs, stream);
+    }
+    hipEvent_t done = nullptr;
+    char *host = htab;
+    if (!host) {
+        const int st = get_stage(stream, P.tables, &host, &done);
+        if (st != CCL_OK)
+            return st;
+    }
+    int st = build_plan(descs, P, base, host, &runs);
     if (st != CCL_OK)
         return st;
-    return hipMemcpy(dtab, tab.data(), tab.size(), hipMemcpyHostToDevice) == hipSuccess ? CCL_OK : CCL_ERR_HIP;
+    if (hipMemcpyAsync(base, host, P.tables, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        (done && hipEventRecord(done, stream) != hipSuccess))
+        return CCL_ERR_HIP;
+    return launch_plan(P, runs, stream);
+}
+
+int run_batch(const Desc *descs, int n, int call_tile, hipStream_t stream) {
+    const Plan P = plan_batch(descs, n, call_tile);
+    void *ws = nullptr;
+    const int st = get_workspace(stream, P.bytes, &ws);
+    if (st != CCL_OK)
+        return st;
+    return run_plan_in(descs, P, stream, static_cast<char *>(ws));
 }
 
 }  // namespace
@@ -520,30 +613,23 @@ extern "C" {
 
 int ccl_label_level(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
                     int32_t *labels, int32_t *num_components, int tile, hipStream_t stream) {
-    int st = check_image(img, H, W, stride, conn, labels);
-    if (st != CCL_OK)
-        return st;
-    if ((st = check_level(level)) != CCL_OK)
-        return st;
-    TileCfg c;
-    if ((st = resolve_tile(tile, &c)) != CCL_OK)
-        return st;
-    Desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR, 0};
-    return run_batch(&d, 1, c, stream);
+    Desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_PAIR, 0, CCL_ORDER_CANONICAL, tile};
+    const int st = check_desc(d);
+    return st != CCL_OK ? st : run_batch(&d, 1, 0, stream);
 }
 
 int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int level, int conn,
                    int32_t *labels, int32_t *num_components, int tile, hipStream_t stream) {
-    int st = check_image(img, H, W, stride, conn, labels);
-    if (st != CCL_OK)
-        return st;
-    if ((st = check_level(level)) != CCL_OK)
-        return st;
-    TileCfg c;
-    if ((st = resolve_tile(tile, &c)) != CCL_OK)
-        return st;
-    Desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_ROW, 1};
-    return run_batch(&d, 1, c, stream);
+    Desc d{img, H, W, stride, conn, labels, num_components, level, CCL_SCAN_ROW, 1, CCL_ORDER_CANONICAL, tile};
+    const int st = check_desc(d);
+    return st != CCL_OK ? st : run_batch(&d, 1, 0, stream);
+}
+
+int ccl_label_provisional(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
+                          int32_t *num_components, int tile, hipStream_t stream) {
+    Desc d{img, H, W, stride, conn, labels, num_components, 0, CCL_SCAN_PAIR, 0, CCL_ORDER_PROVISIONAL, tile};
+    const int st = check_desc(d);
+    return st != CCL_OK ? st : run_batch(&d, 1, 0, stream);
 }
 
 int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
@@ -559,20 +645,15 @@ int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn
 int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream) {
     if (n < 0 || (n > 0 && !descs))
         return CCL_ERR_BATCH;
-    TileCfg c;
-    int st = resolve_tile(tile, &c);
+    int st = check_tile(tile);
     if (st != CCL_OK)
         return st;
     if (n == 0)
         return CCL_OK;
-    for (int i = 0; i < n; i++) {
-        st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
-        if (st == CCL_OK)
-            st = check_opts(descs[i]);
-        if (st != CCL_OK)
+    for (int i = 0; i < n; i++)
+        if ((st = check_desc(descs[i])) != CCL_OK)
             return st;
-    }
-    return run_batch(descs, n, c, stream);
+    return run_batch(descs, n, tile, stream);
 }
 
 int ccl_label_batch(const ccl_image_desc *descs, int n, hipStream_t stream) {
@@ -581,33 +662,34 @@ int ccl_label_batch(const ccl_image_desc *descs, int n, hipStream_t stream) {
     std::vector<Desc> ex((size_t)n);
     for (int i = 0; i < n; i++) {
         const ccl_image_desc &d = descs[i];
-        ex[i] = Desc{d.img, d.H, d.W, d.stride, d.conn, d.labels, d.num_components, 0, CCL_SCAN_PAIR, 0};
+        ex[i] = Desc{d.img, d.H, d.W, d.stride, d.conn, d.labels, d.num_components, 0, CCL_SCAN_PAIR, 0,
+                     CCL_ORDER_CANONICAL, 0};
     }
     return ccl_label_batch_ex(ex.data(), n, 0, stream);
 }
 
 size_t ccl_workspace_bytes(int64_t H, int64_t W, int conn) {
     int8_t dummy;
-    if (check_image(&dummy, H, W, W, conn, &dummy) != CCL_OK)
+    Desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy), nullptr,
+           0, CCL_SCAN_PAIR, 0, CCL_ORDER_CANONICAL, 0};
+    if (check_desc(d) != CCL_OK)
         return 0;
-    TileCfg c;
-    (void)resolve_tile(0, &c);
-    Desc d{reinterpret_cast<const uint8_t *>(&dummy), H, W, W, conn, reinterpret_cast<int32_t *>(&dummy), nullptr, 0,
-           CCL_SCAN_PAIR, 0};
-    return batch_bytes(&d, 1, c, nullptr, nullptr);
+    return batch_bytes(&d, 1, 0);
 }
 
 size_t ccl_batch_workspace_bytes(const ccl_image_desc_ex *descs, int n, int tile) {
-    TileCfg c;
-    if (resolve_tile(tile, &c) != CCL_OK || n < 0 || (n > 0 && !descs))
+    if (check_tile(tile) != CCL_OK || n < 0 || (n > 0 && !descs))
         return 0;
-    for (int i = 0; i < n; i++) {
-        int8_t dummy;
-        if (check_image(&dummy, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, &dummy) != CCL_OK ||
-            check_opts(descs[i]) != CCL_OK)
+    int8_t dummy;
+    std::vector<Desc> v(descs, descs + n);
+    for (Desc &d : v) {
+        // the buffers are not used: only the shapes and options count
+        d.img = reinterpret_cast<const uint8_t *>(&dummy);
+        d.labels = reinterpret_cast<int32_t *>(&dummy);
+        if (check_desc(d) != CCL_OK)
             return 0;
     }
-    return batch_bytes(descs, n, c, nullptr, nullptr);
+    return batch_bytes(v.data(), n, tile);
 }
 
 int ccl_batch_graph_create(const ccl_image_desc_ex *descs, int n, int tile, ccl_graph **out) {
@@ -616,34 +698,27 @@ int ccl_batch_graph_create(const ccl_image_desc_ex *descs, int n, int tile, ccl_
     *out = nullptr;
     if (n <= 0 || !descs)
         return CCL_ERR_BATCH;
-    TileCfg c;
-    int st = resolve_tile(tile, &c);
+    int st = check_tile(tile);
     if (st != CCL_OK)
         return st;
-    for (int i = 0; i < n; i++) {
-        st = check_image(descs[i].img, descs[i].H, descs[i].W, descs[i].stride, descs[i].conn, descs[i].labels);
-        if (st == CCL_OK)
-            st = check_opts(descs[i]);
-        if (st != CCL_OK)
+    for (int i = 0; i < n; i++)
+        if ((st = check_desc(descs[i])) != CCL_OK)
             return st;
-    }
-    std::vector<Layout> lays;
-    std::vector<size_t> offs;
-    const size_t total = batch_bytes(descs, n, c, &lays, &offs);
+    const Plan P = plan_batch(descs, n, tile);
     ccl_graph *g = new ccl_graph();
-    if (hipMalloc(&g->ws, total) != hipSuccess) {
+    if (hipMalloc(&g->ws, P.bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete g;
         return CCL_ERR_NOMEM;
     }
     char *base = static_cast<char *>(g->ws);
-    std::vector<int> grp[kGroups];
-    for (int i = 0; i < n; i++)
-        grp[group_of(descs[i])].push_back(i);
-    size_t at[kGroups] = {0, group_table_bytes(grp[0].size()),
-                          group_table_bytes(grp[0].size()) + group_table_bytes(grp[1].size())};
-    for (int k = 0; k < kGroups && st == CCL_OK; k++)
-        st = upload_group_table(descs, grp[k], lays, offs, base, base + at[k]);
+    // the tables go to the graph's own workspace once, before capture: the
+    // graph holds kernel nodes only
+    std::vector<char> host(P.tables);
+    std::vector<GroupRun> runs;
+    st = build_plan(descs, P, base, host.data(), &runs);
+    if (st == CCL_OK && hipMemcpy(base, host.data(), P.tables, hipMemcpyHostToDevice) != hipSuccess)
+        st = CCL_ERR_HIP;
     hipStream_t cs = nullptr;
     if (st == CCL_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
         st = CCL_ERR_HIP;
@@ -651,9 +726,7 @@ int ccl_batch_graph_create(const ccl_image_desc_ex *descs, int n, int tile, ccl_
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             st = CCL_ERR_HIP;
         } else {
-            int s2 = CCL_OK;
-            for (int k = 0; k < kGroups && s2 == CCL_OK; k++)
-                s2 = run_group(descs, grp[k], lays, offs, base, base + at[k], k, c, cs, true);
+            const int s2 = launch_plan(P, runs, cs);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &graph);
             st = s2 != CCL_OK ? s2 : (e == hipSuccess ? CCL_OK : CCL_ERR_HIP);
@@ -708,7 +781,7 @@ int ccl_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {
         if (it->first.first == dev) {
-            (void)hipFree(it->second.ptr);
+            free_workspace(it->second);
             it = g_ws.erase(it);
         } else {
             ++it;
@@ -762,14 +835,13 @@ int ccl_tile_count(void) { return kNumTiles; }
 int ccl_tile_default(int conn, int scan, int gray) {
     if ((conn != 4 && conn != 8) || (scan != CCL_SCAN_PAIR && scan != CCL_SCAN_ROW) || (gray != 0 && gray != 1))
         return 0;
-    return kDefaultTile[group_of(conn, scan, gray)];
+    return kDefaultTile[kind_of(conn, scan, gray)];
 }
 
 int ccl_tile_config(int id, int *tile_h, int *tile_w) {
-    TileCfg c;
-    int st = resolve_tile(id, &c);
-    if (st != CCL_OK)
-        return st;
+    if (check_tile(id) != CCL_OK)
+        return CCL_ERR_TILE;
+    const TileCfg &c = kTiles[(id ? id : 1) - 1];
     if (tile_h)
         *tile_h = c.nsr;
     if (tile_w)
@@ -795,6 +867,7 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_BUDGET: return "request needs more workspace than a server slot holds";
     case CCL_ERR_TICKET: return "unknown server ticket";
     case CCL_ERR_GRAY: return "gray must be 0 or 1";
+    case CCL_ERR_ORDER: return "unknown output order";
     default: return "unknown status";
     }
 }
@@ -832,7 +905,7 @@ struct ServerSlot {
 struct ccl_server {
     int dev = 0;
     ccl_server_config cfg{};
-    ccl::TileCfg tile{};
+    int tile = 0;                    // tile id of images whose descriptor names none
     size_t ws_bytes = 0;
     std::vector<ccl::ServerSlot> slots;
     std::mutex mu;
@@ -848,9 +921,7 @@ struct ccl_server {
     int error = CCL_OK;              // first HIP failure seen by the scheduler
     std::thread th;
 
-    size_t bytes_of(const ccl::Desc &d) const {
-        return ccl::layout_of(d.H, d.W, ccl::bh_of(d), ccl::tile_for(tile, ccl::group_of(d)), d.gray != 0).bytes;
-    }
+    size_t bytes_of(const ccl::Desc &d) const { return ccl::layout_of(d, ccl::key_of(d, tile)).bytes; }
 
     void finish(ccl::ServerSlot &sl, Clock::time_point now) {
         for (auto &r : sl.batch) {
@@ -866,23 +937,23 @@ struct ccl_server {
     }
 
     // Take the longest queue prefix that fits one slot.  The footprint of a
-    // candidate batch is what run_batch_in will lay out in the slot's
-    // workspace: the table of every launch group, then the image regions.
+    // candidate batch is what plan_batch lays out in the slot's workspace:
+    // the table of every launch group, then the image regions.
     std::vector<ccl::ServerReq> take_batch() {
         std::vector<ccl::ServerReq> b;
-        size_t used = 0;
-        size_t per_group[ccl::kGroups] = {0, 0, 0};
+        std::map<ccl::GroupKey, size_t> members;
+        size_t used = 0, tables = 0;
         int64_t px = 0;
         while (!pending.empty() && (int)b.size() < cfg.max_batch) {
             const ccl::ServerReq &r = pending.front();
             const int64_t n = r.d.H * r.d.W;
-            const int g = ccl::group_of(r.d);
-            per_group[g]++;
-            const size_t need = ccl::tables_bytes(per_group) + used + r.bytes;
-            if (!b.empty() && (px + n > cfg.max_batch_pixels || need > ws_bytes)) {
-                per_group[g]--;
+            const ccl::GroupKey g = ccl::key_of(r.d, tile);
+            const size_t m = members.count(g) ? members[g] : 0;
+            const size_t tables2 = tables - ccl::group_table_bytes(m) + ccl::group_table_bytes(m + 1);
+            if (!b.empty() && (px + n > cfg.max_batch_pixels || tables2 + used + r.bytes > ws_bytes))
                 break;
-            }
+            members[g] = m + 1;
+            tables = tables2;
             used += r.bytes;
             px += n;
             b.push_back(r);
@@ -924,8 +995,10 @@ struct ccl_server {
                     if (r.ready && hipStreamWaitEvent(sl.stream, r.ready, 0) != hipSuccess)
                         st = CCL_ERR_HIP;
                 }
-                if (st == CCL_OK)
-                    st = ccl::run_batch_in(descs.data(), (int)descs.size(), tile, sl.stream, sl.ws, sl.htab);
+                if (st == CCL_OK) {
+                    const ccl::Plan P = ccl::plan_batch(descs.data(), (int)descs.size(), tile);
+                    st = ccl::run_plan_in(descs.data(), P, sl.stream, sl.ws, sl.htab);
+                }
                 if (st == CCL_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess)
                     st = CCL_ERR_HIP;
                 lk.lock();
@@ -960,13 +1033,12 @@ int ccl_server_create(const ccl_server_config *cfg, ccl_server **out) {
     *out = nullptr;
     if (cfg->n_streams < 1 || cfg->max_batch < 1 || cfg->max_batch_pixels < 1 || cfg->hbm_budget == 0)
         return CCL_ERR_BATCH;
-    ccl::TileCfg tc;
-    int st = ccl::resolve_tile(cfg->tile, &tc);
+    int st = ccl::check_tile(cfg->tile);
     if (st != CCL_OK)
         return st;
     ccl_server *s = new ccl_server();
     s->cfg = *cfg;
-    s->tile = tc;
+    s->tile = cfg->tile;
     s->ws_bytes = cfg->hbm_budget / (size_t)cfg->n_streams;
     if (hipGetDevice(&s->dev) != hipSuccess) {
         delete s;
@@ -977,7 +1049,7 @@ int ccl_server_create(const ccl_server_config *cfg, ccl_server **out) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void **>(&sl.htab),
-                          ccl::group_table_bytes((size_t)cfg->max_batch) * ccl::kGroups) != hipSuccess)
+                          ccl::max_tables_bytes(cfg->max_batch)) != hipSuccess)
             st = CCL_ERR_HIP;
         else if (hipMalloc(reinterpret_cast<void **>(&sl.ws), s->ws_bytes) != hipSuccess)
             st = CCL_ERR_NOMEM;
@@ -1003,9 +1075,7 @@ int ccl_server_create(const ccl_server_config *cfg, ccl_server **out) {
 int ccl_server_submit(ccl_server *s, const ccl_image_desc_ex *d, hipStream_t ready, uint64_t *ticket) {
     if (!s || !d || !ticket)
         return CCL_ERR_NULL;
-    int st = ccl::check_image(d->img, d->H, d->W, d->stride, d->conn, d->labels);
-    if (st == CCL_OK)
-        st = ccl::check_opts(*d);
+    const int st = ccl::check_desc(*d);
     if (st != CCL_OK)
         return st;
     ccl::ServerReq r{};

@@ -71,7 +71,9 @@ struct Img {
     CCL_GLOBAL int32_t *bval;        // [NT][CAP]   interior roots before it in its row -> offset -> final label
     CCL_GLOBAL uint16_t *bkey;       // [NT][CAP]   canonical key of boundary component j
     CCL_GLOBAL uint8_t *broot;       // [NT][CAP]   boundary component j is its set's root
-    CCL_GLOBAL int32_t *seg;         // [H][NTX]    roots per (row, tile column) segment -> exclusive scan
+    CCL_GLOBAL int32_t *seg;         // [nseg]      canonical order: roots per (row, tile column) segment,
+                                     //             [H][NTX]; provisional order: roots per tile, [NT];
+                                     //             then their exclusive scan
     CCL_GLOBAL int32_t *blk;         // [nblk]      scan block totals -> exclusive scan
     int64_t stride;
     int32_t H, W, NTY, NTX, conn;
@@ -81,7 +83,13 @@ struct Img {
     int32_t edge0;        // first edge segment (boundary merge kernel)
     int32_t scan0;        // first scan block
     int32_t nblk;
+    int32_t nseg;         // entries of seg
 };
+
+// Output numbering (the ccl_order values): components ranked by smallest
+// raster index, or numbered in the order of their smallest provisional label
+// (tile, then component within the tile).
+enum Order { kCanonical = 0, kProvisional = 1 };
 
 struct Batch {
     const Img *tab;         // device table of n images (n > 1)
@@ -538,7 +546,7 @@ struct ScanLds : RunLds<NSR, TW, BH> {
 
 // Eight waves per SIMD (four workgroups per CU, as the LDS allows): the
 // register allocator is held to the matching scalar-register budget.
-template <int NSR, int TW, int BH>
+template <int NSR, int TW, int BH, int ORD>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_scan(Batch b) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
@@ -633,10 +641,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         __syncthreads();
     }
 
-    // 2. block runs, their ordinals and start positions
+    // 2. block runs, their ordinals and start positions (the starts serve
+    // the canonical keys only)
     const int32_t n_runs = number_runs<NSR, TW, BH, NT>(t, t.GE);
 #pragma unroll
-    for (int k = 0; k < UPT; k++) {
+    for (int k = 0; k < (ORD == kCanonical ? UPT : 0); k++) {
         const int u = tid + k * NT;
         if (u < G::NU) {
             const int R = u / NW, w = u % NW;
@@ -848,10 +857,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         __syncthreads();
     }
     __syncthreads();
-    for (int i = tid; i < G::NM; i += NT)
-        t.late.RK[i] = 0u;
-    for (int r = tid; r < TH; r += NT)
-        t.late.rowcnt[r] = 0;
+    if (ORD == kCanonical) {
+        for (int i = tid; i < G::NM; i += NT)
+            t.late.RK[i] = 0u;
+        for (int r = tid; r < TH; r += NT)
+            t.late.rowcnt[r] = 0;
+    }
     for (int i = tid; i < G::RW; i += NT)
         t.late.RFB[i] = 0u;
     __syncthreads();
@@ -887,25 +898,30 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         if (k < n_runs) {
             const int32_t root = t.P[k] >> 2;
             t.late.RT[k] = (uint16_t)rank_of(t.late.RFB, t.late.RFP, root);
-            same_row = (t.SP[k] / TW) == (t.SP[root] / TW);
+            if (ORD == kCanonical)
+                same_row = (t.SP[k] / TW) == (t.SP[root] / TW);
         }
-        const uint64_t bal = __ballot(same_row);
-        const int wd = (k0 + wave * 64) >> 5;
-        if (lane == 0 && wd < G::RW)
-            t.late.RRB[wd] = (uint32_t)bal;
-        if (lane == 32 && wd + 1 < G::RW)
-            t.late.RRB[wd + 1] = (uint32_t)(bal >> 32);
+        if (ORD == kCanonical) {
+            const uint64_t bal = __ballot(same_row);
+            const int wd = (k0 + wave * 64) >> 5;
+            if (lane == 0 && wd < G::RW)
+                t.late.RRB[wd] = (uint32_t)bal;
+            if (lane == 32 && wd + 1 < G::RW)
+                t.late.RRB[wd + 1] = (uint32_t)(bal >> 32);
+        }
     }
     __syncthreads();
 
     // 5. canonical key of each component: its first pixel in raster order,
     // the minimum over its nodes of the node's first pixel (top row first)
-    for (int c = tid; c < n_comp; c += NT)
-        t.P[c] = 0x7FFFFFFF;
+    if (ORD == kCanonical) {
+        for (int c = tid; c < n_comp; c += NT)
+            t.P[c] = 0x7FFFFFFF;
+    }
     for (int i = tid; i < G::RW; i += NT)
         t.late.RFB[i] = 0u;  // from here on: boundary components
     __syncthreads();
-    for (int k = tid; k < n_runs; k += NT) {
+    for (int k = tid; k < (ORD == kCanonical ? n_runs : 0); k += NT) {
         const int sp = t.SP[k];
         const int R = sp / TW, col = sp % TW;
         // the first pixel of a component lies in the block row of its root
@@ -972,7 +988,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     int32_t n_bound = 0;  // known to the first wave, which exports it
     if (wave == 0)
         n_bound = wave_popcount_prefix(t.late.RFB, t.late.RFP, (n_comp + 31) >> 5, lane);
-    for (int c = tid; c < n_comp; c += NT) {
+    for (int c = tid; c < (ORD == kCanonical ? n_comp : 0); c += NT) {
         if (!((t.late.RFB[c >> 5] >> (c & 31)) & 1u)) {
             const int32_t key = t.P[c];
             atomicOr(&t.late.RK[key >> 5], 1u << (key & 31));
@@ -986,13 +1002,20 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     for (int c = tid; c < n_comp; c += NT) {
         if ((t.late.RFB[c >> 5] >> (c & 31)) & 1u) {
             const int32_t j = rank_of(t.late.RFB, t.late.RFP, c);
-            const int32_t key = t.P[c];
-            const int kr = key / TW, kc = key % TW;
             const uint32_t id = (uint32_t)(cbase + j);
-            const uint32_t gkey = (uint32_t)((y0 + kr) * im.W + x0 + kc);
-            im.bkey[id] = (uint16_t)key;
-            im.bval[id] = popc_before(&t.late.RK[kr * NW], kc);
-            im.uf[id] = ((uint64_t)gkey << 32) | id;
+            if (ORD == kCanonical) {
+                const int32_t key = t.P[c];
+                const int kr = key / TW, kc = key % TW;
+                const uint32_t gkey = (uint32_t)((y0 + kr) * im.W + x0 + kc);
+                im.bkey[id] = (uint16_t)key;
+                im.bval[id] = popc_before(&t.late.RK[kr * NW], kc);
+                im.uf[id] = ((uint64_t)gkey << 32) | id;
+            } else {
+                // the provisional label of a boundary component orders like
+                // its id (tile, then boundary index, which follows the
+                // component ordinal), so the id is its key
+                im.uf[id] = ((uint64_t)id << 32) | id;
+            }
         }
     }
     // edge buffers: boundary index of the component of every edge pixel
@@ -1020,9 +1043,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             v = (uint16_t)rank_of(t.late.RFB, t.late.RFP, t.late.RT[node_at(t, r / G::RB, c)]);
         *dst = v;
     }
-    for (int r = tid; r < TH; r += NT)
-        if (y0 + r < im.H)
-            im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.late.rowcnt[r];
+    if (ORD == kCanonical) {
+        for (int r = tid; r < TH; r += NT)
+            if (y0 + r < im.H)
+                im.seg[(int64_t)(y0 + r) * im.NTX + tx] = t.late.rowcnt[r];
+    }
     // node -> component, two entries per store (an odd count writes one
     // unused entry past the end, inside the tile's capacity)
     uint32_t *grt2 = reinterpret_cast<uint32_t *>(im.rt + (int64_t)ti * G::RCAP);
@@ -1030,7 +1055,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     for (int k = tid; 2 * k < n_runs; k += NT)
         grt2[k] = RT2[k];
     int32_t *gck = im.cf + (int64_t)ti * G::RCAP;
-    for (int c = tid; c < n_comp; c += NT)
+    for (int c = tid; c < (ORD == kCanonical ? n_comp : 0); c += NT)
         gck[c] = t.P[c];
     uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
     for (int i = tid; i < ((n_comp + 31) >> 5); i += NT)
@@ -1364,12 +1389,99 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b, int32_t ntiles) {
 }
 
 // ------------------------------------------------------------------------
+// K3a, provisional order: flatten the boundary components of one tile (as
+// above), then number the tile's roots -- its interior components and the
+// boundary components that are their set's root -- in component order.
+// seg[tile] gets the tile's root count; each local component's slot in cf
+// gets its rank among the tile's roots (a root) or ~(id of its set's root)
+// (a boundary component that is not a root), for the component-label
+// kernel.  One wave per tile, as above.
+// ------------------------------------------------------------------------
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_flatten_prov(Batch b, int32_t ntiles) {
+    using G = Geo<NSR, TW, BH>;
+    __shared__ uint32_t CBs[kWaves][G::RW];   // boundary components (bit per component)
+    __shared__ int32_t CPs[kWaves][G::RW];    // popcount prefix of CB
+    __shared__ uint32_t RBs[kWaves][G::RW];   // roots (bit per component)
+    __shared__ int32_t RPs[kWaves][G::RW];    // popcount prefix of RB
+    __shared__ uint32_t RIDs[kWaves][G::CAP]; // id of the set root of each boundary component
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * kWaves + wv;
+    if (tile >= ntiles)
+        return;
+    const Img &im = find_img(b, tile, kTile);
+    const int ti = tile - im.tile0;
+    const int n_comp = im.tcnt[ti * 4 + 1], n = im.tcnt[ti * 4 + 2];
+    const int ncw = (n_comp + 31) >> 5;
+    uint32_t *CB = CBs[wv], *RB = RBs[wv], *RID = RIDs[wv];
+    int32_t *CP = CPs[wv], *RP = RPs[wv];
+    const uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
+    for (int i = lane; i < ncw; i += 64)
+        CB[i] = gcb[i];
+    const int64_t cbase = (int64_t)ti * G::CAP;
+    // find the set root of every boundary component (all unions are done:
+    // plain loads, as in the canonical form); kept in LDS, so that the
+    // lanes below read what other lanes found
+    int j = lane;
+    uint32_t r = (uint32_t)(cbase + j);
+    while (j < n) {
+        const uint64_t v = im.uf[r];
+        if ((uint32_t)v != r) {
+            r = (uint32_t)v;
+            continue;
+        }
+        RID[j] = r;
+        j += 64;
+        r = (uint32_t)(cbase + j);
+    }
+    wave_sync();
+    wave_popcount_prefix(CB, CP, ncw, lane);
+    wave_sync();
+    // root bitmap: interior components, and boundary components that are
+    // their set's root; one wave ballot covers two words
+    for (int c0 = 0; c0 < n_comp; c0 += 64) {
+        const int c = c0 + lane;
+        bool root = false;
+        if (c < n_comp) {
+            root = true;
+            if ((CB[c >> 5] >> (c & 31)) & 1u) {
+                const int32_t jb = rank_of(CB, CP, c);
+                root = RID[jb] == (uint32_t)(cbase + jb);
+            }
+        }
+        const uint64_t bal = __ballot(root);
+        if (lane == 0)
+            RB[c0 >> 5] = (uint32_t)bal;
+        if (lane == 32 && (c0 >> 5) + 1 < G::RW)
+            RB[(c0 >> 5) + 1] = (uint32_t)(bal >> 32);
+    }
+    wave_sync();
+    const int32_t roots = wave_popcount_prefix(RB, RP, ncw, lane);
+    wave_sync();
+    int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+    for (int c = lane; c < n_comp; c += 64) {
+        const bool root = (RB[c >> 5] >> (c & 31)) & 1u;
+        const bool bnd = (CB[c >> 5] >> (c & 31)) & 1u;
+        if (root) {
+            const int32_t k = rank_of(RB, RP, c);
+            gcf[c] = k;
+            if (bnd)
+                im.bval[cbase + rank_of(CB, CP, c)] = k;
+        } else {
+            gcf[c] = ~(int32_t)RID[rank_of(CB, CP, c)];
+        }
+    }
+    if (lane == 0)
+        im.seg[ti] = roots;
+}
+
+// ------------------------------------------------------------------------
 // K4a / K4b: exclusive scan of the segment counts in raster order.
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_scan_blocks(Batch b) {
     const Img &im = find_img(b, blockIdx.x, kScan);
     const int c = blockIdx.x - im.scan0;
-    const int64_t L = (int64_t)im.H * im.NTX;
+    const int64_t L = im.nseg;
     const int64_t base = (int64_t)c * kScanChunk + threadIdx.x * 16;
     int32_t v[16];
     int32_t sum = 0;
@@ -1506,6 +1618,37 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b, int32_t ntile
     }
     for (int c = lane + KR * 64; c < n_comp; c += 64)
         second(c, gck[c]);
+}
+
+// ------------------------------------------------------------------------
+// K4c, provisional order: final label of every local component.  A root's
+// label is 1 + the roots of the tiles before its tile (the scan of the
+// per-tile counts) + its rank in its tile; a boundary component that is not
+// a root takes its set root's label, computed the same way from the root's
+// tile and rank.  One wave per tile.
+// ------------------------------------------------------------------------
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_comp_labels_prov(Batch b, int32_t ntiles) {
+    using G = Geo<NSR, TW, BH>;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * kWaves + wv;
+    if (tile >= ntiles)
+        return;
+    const Img &im = find_img(b, tile, kTile);
+    const int ti = tile - im.tile0;
+    const int n_comp = im.tcnt[ti * 4 + 1];
+    const int32_t base = 1 + im.seg[ti] + im.blk[ti / kScanChunk];
+    int32_t *gcf = im.cf + (int64_t)ti * G::RCAP;
+    for (int c = lane; c < n_comp; c += 64) {
+        const int32_t v = gcf[c];
+        if (v >= 0) {
+            gcf[c] = base + v;
+        } else {
+            const uint32_t rid = ~(uint32_t)v;
+            const int rt = (int)(rid / G::CAP);
+            gcf[c] = 1 + im.seg[rt] + im.blk[rt / kScanChunk] + im.bval[rid];
+        }
+    }
 }
 
 // ------------------------------------------------------------------------

@@ -89,7 +89,8 @@ class Server:
         self._inflight = collections.deque()
 
     def submit(self, img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None, level: int = 0,
-               scan: int = ccl.SCAN_PAIR, gray: bool = False, ready=True) -> Request:
+               scan: int = ccl.SCAN_PAIR, gray: bool = False, ready=True, order: int = ccl.CANONICAL,
+               tile: int = 0) -> Request:
         """Queue one image.  ready: True = the image and `out` are ready once
         the current stream's work so far is (the library waits for it on the
         device), a torch stream = once that stream's work is, False = now."""
@@ -98,7 +99,8 @@ class Server:
             out = torch.empty((H, W), dtype=torch.int32, device=img.device)
         ccl._check_out(out, img)
         d = ccl.ImageDescEx(img=img.data_ptr(), H=H, W=W, stride=stride, conn=int(conn), labels=out.data_ptr(),
-                            num_components=None, level=int(level), scan=int(scan), gray=int(bool(gray)))
+                            num_components=None, level=int(level), scan=int(scan), gray=int(bool(gray)),
+                            order=int(order), tile=int(tile))
         t = ctypes.c_uint64()
         rs = None if ready is False else ccl._stream_handle(None if ready is True else ready)
         st = ccl._lib.ccl_server_submit(self._h, ctypes.byref(d), rs, ctypes.byref(t))

@@ -27,6 +27,7 @@ int64_t oracle_paremsp(const uint8_t *img, int64_t H, int64_t W, int64_t stride,
 int64_t oracle_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels);
 int64_t oracle_canonical(int32_t *labels, int64_t H, int64_t W);
 void oracle_merge_pairs(int32_t *p, const int32_t *pairs, int64_t m);
+int64_t oracle_provisional(int32_t *labels, int64_t H, int64_t W, int64_t K, int th, int tw, int block);
 int32_t oracle_flatten(int32_t *p, int32_t count);
 
 static uint64_t rng_state = 0x1234567887654321ull;
@@ -102,6 +103,15 @@ static void check_binary(const uint8_t *img, int H, int W, int32_t *ref, int32_t
         for (int t = 1; t <= 4; t++) {
             k = oracle_paremsp(img, H, W, W, conn, got, t);
             expect_same("paremsp", got, k, ref, kref, H, W, conn);
+        }
+        /* provisional renumbering: a permutation of 1..K that renumbers back */
+        memcpy(got, ref, sizeof(int32_t) * (size_t)H * (size_t)W);
+        k = oracle_provisional(got, H, W, kref, 2, 3, conn == 8 ? 2 : 1);
+        if (k == kref) {
+            k = oracle_canonical(got, H, W);
+            expect_same("provisional renumbered", got, k, ref, kref, H, W, conn);
+        } else {
+            expect_same("provisional count", got, k, ref, kref, H, W, conn);
         }
     }
 }

@@ -92,6 +92,16 @@ def test_status_codes_on_host():
     arr[1].gray = 3
     assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_GRAY"]
     arr[1].gray = 0
+    arr[1].order = 2
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_ORDER"]
+    arr[1].order = 0
+    arr[0].tile = 8
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_TILE"]
+    arr[0].tile = -1
+    assert lib.ccl_label_batch_ex(arr, 2, 0, None) == S["CCL_ERR_TILE"]
+    arr[0].tile = 0
+    assert lib.ccl_label_provisional(dummy, 10, 10, 10, 8, dummy, None, 9, None) == S["CCL_ERR_TILE"]
+    assert lib.ccl_label_provisional(dummy, 10, 10, 10, 3, dummy, None, 0, None) == S["CCL_ERR_CONN"]
     assert lib.ccl_label_gray(dummy, 10, 10, 10, 300, 8, dummy, None, 0, None) == S["CCL_ERR_LEVEL"]
     assert lib.ccl_label_gray(dummy, 10, 10, 10, 0, 5, dummy, None, 0, None) == S["CCL_ERR_CONN"]
     arr[1].conn = 5
@@ -111,7 +121,7 @@ def test_descriptor_layouts_match_the_header(tmp_path):
     from paper_1606_05973_amd import ccl
     fields = {"ccl_image_desc": (ccl.ImageDesc, ["img", "H", "W", "stride", "conn", "labels", "num_components"]),
               "ccl_image_desc_ex": (ccl.ImageDescEx, ["img", "H", "W", "stride", "conn", "labels", "num_components",
-                                                      "level", "scan", "gray"]),
+                                                      "level", "scan", "gray", "order", "tile"]),
               "ccl_server_config": (ccl.ServerConfig, ["n_streams", "max_batch", "max_batch_pixels", "hbm_budget",
                                                        "tile"]),
               "ccl_server_stats": (ccl.ServerStats, ["submitted", "completed", "rejected", "batches",
@@ -186,6 +196,12 @@ def test_workspace_bytes():
     # the one-row scan under 8-connectivity tiles like 4-connectivity
     assert ccl.workspace_bytes(1000, 1000, 8, scan=ccl.SCAN_ROW) == ccl.workspace_bytes(1000, 1000, 4)
     assert ccl.workspace_bytes(1000, 1000, 8, scan=7) == 0
+    # provisional order scans one count per tile instead of one per (row, tile column)
+    assert 0 < ccl.batch_workspace_bytes([(1000, 1000)], order=ccl.PROVISIONAL) < a
+    # images of different tiles or orders form separate launch groups (a table each)
+    mixed = ccl.batch_workspace_bytes([(300, 300)] * 4, tiles=[1, 2, 1, 2])
+    same = ccl.batch_workspace_bytes([(300, 300)] * 4, tiles=[1, 1, 1, 1])
+    assert mixed > 0 and same > 0 and mixed != same
 
 
 def test_product_path_is_independent_of_the_oracle():

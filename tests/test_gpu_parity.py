@@ -495,3 +495,85 @@ def test_gray_batch_and_full_size(ccl):
         assert np.array_equal(o.cpu().numpy(), ref)
     img = (inputs.gray(16384, 16384, 6.0, seed=5, device=DEV) // 32).contiguous()
     _gray_check(ccl, img, 8, what="16384^2 quantized field")
+
+
+# ------------------------------------------------------- provisional order
+def _prov_ref(ccl, img_host, conn, tile=0, scan=0, gray=False):
+    th, tw = ccl.tile_shape(tile, conn, scan, gray)
+    block = 2 if (conn == 8 and scan == ccl.SCAN_PAIR and not gray) else 1
+    return oracle.provisional(img_host, conn, th, tw, block, gray_levels=gray)
+
+
+def _prov_check(ccl, img, conn, tile=0, what=""):
+    say(f"case provisional {what} shape={tuple(img.shape)} conn={conn} tile={tile}")
+    k = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    got = ccl.label_provisional(img, conn, tile=tile, num_components=k)
+    torch.cuda.synchronize()
+    ref, kref = _prov_ref(ccl, img.cpu().numpy(), conn, tile)
+    g = got.cpu().numpy()
+    if not np.array_equal(g, ref):
+        bad = np.argwhere(g != ref)
+        r, c = bad[0]
+        raise AssertionError(f"provisional {what}: {len(bad)} pixels differ; first at {(r, c)} gpu={g[r, c]} "
+                             f"oracle={ref[r, c]}")
+    assert int(k.item()) == kref
+    return g, kref
+
+
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("conn", [8, 4])
+def test_provisional_shapes(ccl, shape, conn):
+    """Paper-order labels (the flatten's numbering over tile-major provisional
+    labels) equal the oracle's numbering pixel for pixel; they are exactly
+    1..K and renumber to the canonical labels."""
+    H, W = shape
+    for p in (0.1, 0.5, 0.9):
+        img = inputs.bernoulli(H, W, p, seed=H * 5 + W, device=DEV)
+        got, k = _prov_check(ccl, img, conn, what=f"p={p}")
+        if k:
+            assert got.max() == k and np.unique(got[got > 0]).size == k
+        canon = oracle.cclremsp(img.cpu().numpy(), conn)[0]
+        assert np.array_equal(oracle.canonical(got)[0], canon)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_provisional_every_tile_and_pattern(ccl, conn):
+    img = inputs.bernoulli(700, 900, 0.45, seed=3, device=DEV)
+    for tile in range(1, len(ccl.tile_configs()) + 1):
+        _prov_check(ccl, img, conn, tile=tile, what="tile sweep")
+    for name in inputs.ADVERSARIAL:
+        _prov_check(ccl, inputs.adversarial(name, 600, 1100, device=DEV), conn, what=name)
+    g = inputs.grf(777, 1111, 6.0, 0.4, seed=4, device=DEV)
+    _prov_check(ccl, g, conn, what="grf")
+
+
+def test_provisional_batch_mix(ccl):
+    """Provisional and canonical images, scans, gray levels, thresholds and
+    per-image tiles in one batch: every image as its own oracle says."""
+    specs = inputs.batch_specs(14, seed=12, max_side=700)
+    imgs = [inputs.make(s_, device=DEV) for s_ in specs]
+    imgs[3] = (inputs.gray(imgs[3].shape[0], imgs[3].shape[1], 3.0, seed=3, device=DEV) // 40).contiguous()
+    n = len(imgs)
+    conns = [8 if i % 3 else 4 for i in range(n)]
+    orders = [ccl.PROVISIONAL if i % 2 else ccl.CANONICAL for i in range(n)]
+    scans = [ccl.SCAN_ROW if i in (5, 9) else ccl.SCAN_PAIR for i in range(n)]
+    grays = [i == 3 for i in range(n)]
+    tiles = [0, 2, 3, 0, 5, 6, 1, 7, 0, 4, 2, 0, 3, 1]
+    k = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    say("case provisional batch mix")
+    outs = ccl.label_batch(imgs, conns, num_components=k, order=orders, scan=scans, gray=grays, tiles=tiles)
+    torch.cuda.synchronize()
+    for i, img in enumerate(imgs):
+        host = img.cpu().numpy()
+        if orders[i] == ccl.PROVISIONAL:
+            ref, kref = _prov_ref(ccl, host, conns[i], tiles[i], scans[i], grays[i])
+        else:
+            ref, kref = (oracle.gray if grays[i] else oracle.cclremsp)(host, conns[i])
+        assert np.array_equal(outs[i].cpu().numpy(), ref), i
+        assert int(k[i].item()) == kref, i
+
+
+@pytest.mark.parametrize("side,p,conn", [(21568, 0.5, 8), (16384, 0.593, 4)])
+def test_provisional_full_size(ccl, side, p, conn):
+    img = inputs.bernoulli(side, side, p, seed=0, device=DEV)
+    _prov_check(ccl, img, conn, what=f"{side}^2 p={p}")

@@ -474,3 +474,82 @@ def test_gray_planted_mistakes_are_caught(tmp_path, i):
         if caught:
             break
     assert caught, f"gray mutant {i} survived"
+
+
+# ------------------------------------------------------- provisional order
+ROOT_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "provisional")
+
+
+def _read_prov_golden(path):
+    """Fixture: a `tile th tw block` line, then image / labels8 / labels4."""
+    lines = [l.split() for l in open(path) if l.strip() and not l.lstrip().startswith("#")]
+    th, tw, block = (int(v) for v in lines[0][1:4])
+    img, out = None, {}
+    sec, rows, k = None, [], None
+    for l in lines[1:] + [["end"]]:
+        if l[0] in ("image", "labels8", "labels4", "end"):
+            if sec == "image":
+                img = np.array(rows, dtype=np.uint8)
+            elif sec:
+                out[int(sec[-1])] = (np.array(rows, dtype=np.int32), k)
+            sec, rows, k = l[0], [], (int(l[1]) if len(l) > 1 else None)
+        else:
+            rows.append([int(v) for v in l])
+    return img, th, tw, block, out
+
+
+@pytest.mark.parametrize("name", ["tiles_4x4.txt", "pairs_2x4.txt"])
+def test_provisional_golden(name):
+    """Hand-derived provisional numberings (tile order, node order inside a
+    tile), for the oracle and for the step-by-step reference alike."""
+    img, th, tw, block, want = _read_prov_golden(os.path.join(ROOT_GOLDEN, name))
+    for conn, (labels, k) in want.items():
+        got, kk = oracle.provisional(img, conn, th, tw, block)
+        assert np.array_equal(got, labels) and kk == k, (name, conn)
+        got2, k2 = _pins.provisional_by_steps(img, conn, th, tw, block)
+        assert np.array_equal(got2, labels) and k2 == k, (name, conn)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_provisional_against_steps(conn):
+    """The oracle's provisional numbering (ranking sets by their smallest
+    (tile, block row, column)) equals the paper's steps done one by one:
+    per-tile labels in node order with per-tile label ranges, unions across
+    tile edges, then Algorithm 3's consecutive numbering.  Also: the same
+    partition as the canonical labels, labels exactly 1..K."""
+    rng = np.random.default_rng(5)
+    cases = 0
+    for (H, W) in [(1, 9), (7, 1), (6, 9), (9, 14), (13, 11), (16, 16)]:
+        for (th, tw) in [(2, 4), (4, 8), (3, 5), (16, 32)]:
+            for block in ((1, 2) if conn == 8 else (1,)):
+                if th % block:
+                    continue
+                for p in (0.3, 0.6):
+                    img = (rng.random((H, W)) < p).astype(np.uint8)
+                    got, k = oracle.provisional(img, conn, th, tw, block)
+                    ref, kref = _pins.provisional_by_steps(img, conn, th, tw, block)
+                    assert k == kref and np.array_equal(got, ref), (H, W, th, tw, block, p)
+                    canon, kc = oracle.cclremsp(img, conn)
+                    assert kc == k and np.array_equal(oracle.canonical(got)[0], canon)
+                    if k:
+                        assert set(np.unique(got[got > 0])) == set(range(1, k + 1))
+                    cases += 1
+    assert cases >= 48
+    # gray levels: runs of equal values in single rows
+    for (H, W) in [(8, 10), (12, 7)]:
+        img = rng.integers(0, 3, (H, W)).astype(np.uint8)
+        got, k = oracle.provisional(img, conn, 4, 4, 1, gray_levels=True)
+        ref, kref = _pins.provisional_by_steps(img, conn, 4, 4, 1, gray=True)
+        assert k == kref and np.array_equal(got, ref)
+
+
+def test_provisional_special_cases():
+    """One tile and single-row nodes: provisional order is raster order of
+    each set's first pixel, i.e. the canonical numbering."""
+    rng = np.random.default_rng(9)
+    for conn in (8, 4):
+        img = (rng.random((40, 50)) < 0.5).astype(np.uint8)
+        got, _ = oracle.provisional(img, conn, 64, 64, 1)
+        assert np.array_equal(got, oracle.cclremsp(img, conn)[0])
+        zeros = np.zeros((5, 7), np.uint8)
+        assert oracle.provisional(zeros, conn, 2, 4, 1)[1] == 0
