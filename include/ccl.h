@@ -52,7 +52,8 @@ typedef enum {
     CCL_ERR_BUDGET = -13,   /* request needs more workspace than a server slot  */
     CCL_ERR_TICKET = -14,   /* unknown server ticket                            */
     CCL_ERR_GRAY = -15,     /* gray flag other than 0 or 1                      */
-    CCL_ERR_ORDER = -16     /* unknown output order                             */
+    CCL_ERR_ORDER = -16,    /* unknown output order                             */
+    CCL_ERR_SCRATCH = -17   /* image needs more than ccl_label_noalloc's static scratch */
 } ccl_status;
 
 /*
@@ -209,6 +210,30 @@ int ccl_label_gray(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int
  */
 int ccl_label_provisional(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
                           int32_t *labels, int32_t *num_components, int tile, hipStream_t stream);
+
+/*
+ * ccl_label_noalloc -- ccl_label_ex (default tile) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or other
+ * allocating routine and records no profiling events.  Its workspace is a
+ * static device array of CCL_NOALLOC_SCRATCH_BYTES that every device the
+ * library runs on holds until the process ends (looked up on the call's
+ * first use of a device).
+ *   img, H, W, stride, conn, labels, num_components, stream
+ *           as for ccl_label_ex (caller-owned device memory; num_components
+ *           may be NULL).
+ * Limit: images whose ccl_workspace_bytes(H, W, conn) exceeds
+ * CCL_NOALLOC_SCRATCH_BYTES return CCL_ERR_SCRATCH with nothing launched
+ * (4096 x 4096 fits at both connectivities).  Other argument errors as for
+ * ccl_label.  All calls on one device share the one array and it keeps the
+ * last call's contents: calls that overlap on one device (different streams
+ * without ordering between them) race and give undefined labels; calls on
+ * one stream are ordered by the stream.  The output is the same as
+ * ccl_label's.
+ */
+#define CCL_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+int ccl_label_noalloc(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
+                      int32_t *labels, int32_t *num_components, hipStream_t stream);
 
 /* One image of an extended batch.  The first seven fields are those of
  * ccl_image_desc; the options are as in ccl_label_level / ccl_label_gray /

@@ -51,6 +51,8 @@ _lib.ccl_label_gray.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_i
 _lib.ccl_label_gray.restype = ctypes.c_int
 _lib.ccl_label_provisional.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _i32p, ctypes.c_int, _stream]
 _lib.ccl_label_provisional.restype = ctypes.c_int
+_lib.ccl_label_noalloc.argtypes = [_u8p, _i64, _i64, _i64, ctypes.c_int, _i32p, _i32p, _stream]
+_lib.ccl_label_noalloc.restype = ctypes.c_int
 _lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), ctypes.c_int, _stream]
 _lib.ccl_label_batch.restype = ctypes.c_int
 _lib.ccl_label_batch_ex.argtypes = [ctypes.POINTER(ImageDescEx), ctypes.c_int, ctypes.c_int, _stream]
@@ -117,7 +119,9 @@ STATUS = {
     "CCL_ERR_TOO_LARGE": -5, "CCL_ERR_NOMEM": -6, "CCL_ERR_HIP": -7, "CCL_ERR_TILE": -8,
     "CCL_ERR_CAPTURE": -9, "CCL_ERR_BATCH": -10, "CCL_ERR_LEVEL": -11, "CCL_ERR_SCAN": -12,
     "CCL_ERR_BUDGET": -13, "CCL_ERR_TICKET": -14, "CCL_ERR_GRAY": -15, "CCL_ERR_ORDER": -16,
+    "CCL_ERR_SCRATCH": -17,
 }
+NOALLOC_SCRATCH_BYTES = 96 << 20   # CCL_NOALLOC_SCRATCH_BYTES: static workspace of ccl_label_noalloc
 SCAN_PAIR, SCAN_ROW = 0, 1   # ccl_scan: two-row (default) / one-row tile-local scan
 CANONICAL, PROVISIONAL = 0, 1   # ccl_order: smallest raster index (default) / the flatten's provisional order
 
@@ -245,6 +249,21 @@ def label_gray(img: torch.Tensor, conn: int = 8, out: torch.Tensor | None = None
     nc = num_components.data_ptr() if num_components is not None else None
     _check(_lib.ccl_label_gray(img.data_ptr(), H, W, stride, int(level), int(conn), out.data_ptr(), nc,
                                int(tile), _stream_handle(stream)))
+    return out
+
+
+def label_noalloc(img: torch.Tensor, conn: int, out: torch.Tensor, num_components: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """ccl_label_noalloc: label() with the library's static scratch as its
+    workspace; allocates nothing, so `out` must be given.  Images that need
+    more than NOALLOC_SCRATCH_BYTES of workspace raise CCLError
+    (CCL_ERR_SCRATCH)."""
+    H, W, stride = _img_geometry(img)
+    _check_out(out, img)
+    _check_counts(num_components, 1, img.device)
+    nc = num_components.data_ptr() if num_components is not None else None
+    _check(_lib.ccl_label_noalloc(img.data_ptr(), H, W, stride, int(conn), out.data_ptr(), nc,
+                                  _stream_handle(stream)))
     return out
 
 

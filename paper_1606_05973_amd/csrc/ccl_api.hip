@@ -235,6 +235,41 @@ int get_stage(hipStream_t stream, size_t need, char **out, hipEvent_t *done) {
     return CCL_OK;
 }
 
+// ----------------------------------------------------- static scratch
+// Workspace of ccl_label_noalloc: a file-scope device array, so that the
+// call allocates nothing.  The loader gives every device the library runs on
+// its own copy, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: kernels get the device address that
+// hipGetSymbolAddress reports, looked up once per device with that device
+// current.  Every call on a device shares the array, so calls that overlap
+// on one device race (calls on one stream are ordered by the stream).  No
+// kernel relies on zeroed workspace (each writes what it later reads), so
+// nothing is cleared between calls.
+__device__ __align__(256) char scratch[CCL_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_at[kMaxDevices];  // device address of `scratch` per device, once looked up
+
+int scratch_of_current_device(char **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return CCL_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices)
+        return CCL_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return CCL_ERR_HIP;
+        }
+        g_scratch_at[dev] = p;
+    }
+    *out = static_cast<char *>(g_scratch_at[dev]);
+    return CCL_OK;
+}
+
 void free_workspace(Workspace &w) {
     (void)hipFree(w.ptr);
     for (int i = 0; i < 2; i++) {
@@ -309,10 +344,11 @@ struct PhaseMarks {
     std::vector<hipEvent_t> ev;
     hipStream_t s;
     bool on;
-    explicit PhaseMarks(hipStream_t st) : s(st) {
+    // allow = false: no events at all (the allocation-free entry point)
+    PhaseMarks(hipStream_t st, bool allow) : s(st) {
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            on = g_prof_on;
+            on = allow && g_prof_on;
         }
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (on && (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone))
@@ -354,12 +390,12 @@ int persistent_groups(int threads) {
 }
 
 template <int NSR, int TW, int BH, int ORD>
-int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg, hipStream_t s) {
+int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg, hipStream_t s, bool marks) {
     if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
         return CCL_ERR_TOO_LARGE;
     const dim3 blk(kThreads);
     const dim3 tile_groups((uint32_t)((tiles + kWaves - 1) / kWaves));
-    PhaseMarks pm(s);
+    PhaseMarks pm(s, marks);
     pm.mark();
     hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH, ORD>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     pm.mark();
@@ -397,11 +433,11 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
 }
 
 int dispatch(const GroupKey &g, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
-             hipStream_t s) {
+             hipStream_t s, bool marks = true) {
     const TileCfg &c = kTiles[g.tile - 1];
 #define CCL_ORD(N_, W_, B_) \
-    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, edges, blocks, nimg, s) \
-                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, edges, blocks, nimg, s))
+    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, edges, blocks, nimg, s, marks) \
+                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, edges, blocks, nimg, s, marks))
 #define CCL_TILE_CASE(N_, W_)                                                                       \
     if (c.nsr == N_ && c.tw == W_)                                                                  \
         return g.kind == kPair ? CCL_ORD(N_, W_, 2) : g.kind == kRow ? CCL_ORD(N_, W_, 1) : CCL_ORD(N_, W_, 0);
@@ -465,6 +501,18 @@ Plan plan_batch(const Desc *descs, int n, int call_tile) {
 
 size_t batch_bytes(const Desc *descs, int n, int call_tile) { return plan_batch(descs, n, call_tile).bytes; }
 
+// Labeling-pass store form an image allows: 16-byte stores need W % 4 == 0
+// and 16-byte aligned labels; very wide rows need the any-width form.  A
+// group takes the most general form any of its images needs.
+int store_form(const Desc &d) {
+    static_assert(kStoreAny < kStore4 && kStore4 < kStore16, "store forms ordered from the most general");
+    if (d.W > kVecMaxW)
+        return kStoreAny;
+    if (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0)
+        return kStore4;
+    return kStore16;
+}
+
 // One group's launch arguments, its table written to `tab_bytes` (host).
 struct GroupRun {
     Batch b;
@@ -495,10 +543,7 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
         blocks += P.lays[i].nblk;
         if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
             return CCL_ERR_TOO_LARGE;
-        if (d.W > kVecMaxW)
-            b.store = kStoreAny;
-        else if (b.store == kStore16 && (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0))
-            b.store = kStore4;
+        b.store = std::min(b.store, store_form(d));
     }
     if (n == 1) {
         b.one = tab[0];
@@ -640,6 +685,30 @@ int ccl_label_ex(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int c
 int ccl_label(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
               hipStream_t stream) {
     return ccl_label_ex(img, H, W, stride, conn, labels, nullptr, 0, stream);
+}
+
+int ccl_label_noalloc(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
+                      int32_t *num_components, hipStream_t stream) {
+    const Desc d{img, H, W, stride, conn, labels, num_components, 0, CCL_SCAN_PAIR, 0, CCL_ORDER_CANONICAL, 0};
+    int st = check_desc(d);
+    if (st != CCL_OK)
+        return st;
+    // the same layout as a ccl_label call: one image region after a table
+    // slot, so that ccl_workspace_bytes states what the call needs
+    const GroupKey g = key_of(d, 0);
+    const Layout L = layout_of(d, g);
+    const size_t at = group_table_bytes(1);
+    if (at + L.bytes > (size_t)CCL_NOALLOC_SCRATCH_BYTES)
+        return CCL_ERR_SCRATCH;
+    char *base = nullptr;
+    if ((st = scratch_of_current_device(&base)) != CCL_OK)
+        return st;
+    // a single image travels in the kernel arguments (no table upload)
+    Batch b{};
+    b.n = 1;
+    b.store = store_form(d);
+    b.one = make_img(d, L, base + at);
+    return dispatch(g, b, L.NT, L.nedge, L.nblk, 1, stream, false);
 }
 
 int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream) {
@@ -868,6 +937,7 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_TICKET: return "unknown server ticket";
     case CCL_ERR_GRAY: return "gray must be 0 or 1";
     case CCL_ERR_ORDER: return "unknown output order";
+    case CCL_ERR_SCRATCH: return "image needs more workspace than the static scratch of ccl_label_noalloc holds";
     default: return "unknown status";
     }
 }

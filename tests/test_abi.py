@@ -145,6 +145,25 @@ def test_descriptor_layouts_match_the_header(tmp_path):
             assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
 
 
+def test_noalloc_checks_on_host():
+    """ccl_label_noalloc rejects bad arguments and images beyond its static
+    scratch before any device call; the limit is the header's."""
+    from paper_1606_05973_amd import ccl
+    S = ccl.STATUS
+    lib = ccl._lib
+    dummy = 4096  # never dereferenced: the checks fail first
+    assert lib.ccl_label_noalloc(None, 10, 10, 10, 8, dummy, None, None) == S["CCL_ERR_NULL"]
+    assert lib.ccl_label_noalloc(dummy, 10, 0, 10, 8, dummy, None, None) == S["CCL_ERR_SHAPE"]
+    assert lib.ccl_label_noalloc(dummy, 10, 10, 10, 5, dummy, None, None) == S["CCL_ERR_CONN"]
+    assert lib.ccl_label_noalloc(dummy, 8192, 8192, 8192, 8, dummy, None, None) == S["CCL_ERR_SCRATCH"]
+    assert lib.ccl_label_noalloc(dummy, 1, 20000000, 20000000, 8, dummy, None, None) == S["CCL_ERR_SCRATCH"]
+    m = re.search(r"#define CCL_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == ccl.NOALLOC_SCRATCH_BYTES
+    for conn in (4, 8):
+        assert 0 < lib.ccl_workspace_bytes(4096, 4096, conn) <= ccl.NOALLOC_SCRATCH_BYTES
+    assert lib.ccl_workspace_bytes(8192, 8192, 8) > ccl.NOALLOC_SCRATCH_BYTES
+
+
 def test_strerror_and_tiles():
     from paper_1606_05973_amd import ccl
     for code in [0, *ccl.STATUS.values()]:
