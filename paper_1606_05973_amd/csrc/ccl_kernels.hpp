@@ -824,6 +824,17 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             }
         }
         __syncthreads();
+        if (r0 == 0) {
+            // one pointer-jumping round over the direct links: every node
+            // takes its grandparent, which halves the chains of direct links
+            // that the union steps and the flatten walk (a concurrent update
+            // leaves an ancestor either way, so the sets do not change)
+            for (int k = tid; k < n_runs; k += NT) {
+                const int32_t p = aload<WG>(t.P + k);
+                astore<WG>(t.P + k, aload<WG>(at(p)));
+            }
+            __syncthreads();
+        }
         // Each lane steps its own union (one load pair and one CAS per step)
         // and takes its next pair as soon as the current union ends.
         const int np = min(n_pairs - r0, ScanLds<NSR, TW, BH>::PRCAP);
@@ -1823,12 +1834,23 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
         const uint32_t nrec = left < (int64_t)kDropped ? (uint32_t)left : kDropped;
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc(im.labels + (int64_t)y0 * im.W, 0, (int)nrec, kBufferWord3);
+        // (loops with compile-time trip counts: rows wave, wave + 8, ...;
+        // fully unrolled, so each wave issues its stores back to back)
+        constexpr int NWV = NT / 64;
+        constexpr int RPW = (TH + NWV - 1) / NWV;
         if (STORE == kStore16) {
+            constexpr int QPL = (TW / 4 + 63) / 64;
 #pragma unroll
-            for (int r = wave; r < TH; r += NT / 64) {
+            for (int i = 0; i < RPW; i++) {
+                const int r = wave + i * NWV;
+                if (TH % NWV != 0 && r >= TH)
+                    break;
                 const int R = r / G::RB;
 #pragma unroll
-                for (int q = lane; q < TW / 4; q += 64) {
+                for (int j = 0; j < QPL; j++) {
+                    const int q = lane + 64 * j;
+                    if ((TW / 4) % 64 != 0 && q >= TW / 4)
+                        break;
                     const int c0 = q * 4;
                     const int w = c0 >> 5, b0 = c0 & 31;
                     const uint32_t m = t.M[r * NW + w] >> b0;
@@ -1845,7 +1867,10 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
             }
         } else if (STORE == kStore4) {
 #pragma unroll
-            for (int r = wave; r < TH; r += NT / 64) {
+            for (int i = 0; i < RPW; i++) {
+                const int r = wave + i * NWV;
+                if (TH % NWV != 0 && r >= TH)
+                    break;
                 const int R = r / G::RB;
 #pragma unroll
                 for (int e = 0; e < TW / 64; e++) {
