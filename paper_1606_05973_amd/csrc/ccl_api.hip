@@ -397,7 +397,17 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     const dim3 tile_groups((uint32_t)((tiles + kWaves - 1) / kWaves));
     PhaseMarks pm(s, marks);
     pm.mark();
-    hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH, ORD>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
+    if constexpr (BH != 0) {
+        // row pairs and single rows: the compact form, then the tiles with
+        // more nodes than it holds (a grid of at least tiles / 64 groups)
+        hipLaunchKernelGGL((k_tile_scan_c<NSR, TW, BH, ORD>), dim3((uint32_t)tiles), dim3(kScanThreadsC), 0, s, b);
+        const int64_t rest = std::min<int64_t>(
+            tiles, std::max<int64_t>(persistent_groups<k_tile_scan_rest<NSR, TW, BH, ORD>>(kTileThreads), (tiles + 63) / 64));
+        hipLaunchKernelGGL((k_tile_scan_rest<NSR, TW, BH, ORD>), dim3((uint32_t)rest), dim3(kTileThreads), 0, s, b,
+                           (int32_t)tiles);
+    } else {
+        hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH, ORD>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
+    }
     pm.mark();
     if (edges > 0)
         hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((merge_split(BH) * edges + kThreads - 1) / kThreads)),

@@ -513,44 +513,57 @@ __device__ __forceinline__ int32_t upper_node(int pc, uint64_t wU, int32_t bU) {
     return bU + __popcll(wU << (62 - pc));
 }
 
+// Node capacity of the tile scan's LDS arrays (a multiple of 32).  The full
+// form holds the most nodes a tile can have (G::RCAP); the compact form holds
+// 9/16 of that, which covers every i.i.d. image: a run of the scanned rows
+// starts at a given column with probability q(1 - q) <= 1/4 (q = that the
+// column is occupied), i.e. 1/2 of the capacity on average, with a spread of
+// a few dozen nodes per tile.  A tile with more nodes (stripes,
+// checkerboards) is left to the full form.
 template <int NSR, int TW, int BH>
+constexpr int compact_cap() { return Geo<NSR, TW, BH>::RCAP / 16 * 9; }
+
+template <int NSR, int TW, int BH, int CAPN>
 struct ScanLate {
     using G = Geo<NSR, TW, BH>;
-    uint16_t RT[G::RCAP];   // component ordinal of each node
-    uint32_t RRB[G::RW];    // node lies in the block row of its root (bit per node)
-    uint32_t RFB[G::RW];    // root nodes (bit per node); later boundary components (bit per component)
-    int32_t RFP[G::RW];
+    static constexpr int CW = CAPN / 32;
+    uint16_t RT[CAPN];      // component ordinal of each node
+    uint32_t RRB[CW];       // node lies in the block row of its root (bit per node)
+    uint32_t RFB[CW];       // root nodes (bit per node); later boundary components (bit per component)
+    int32_t RFP[CW];
     uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
     int32_t rowcnt[G::TH];
     int32_t ncomp;          // local component count, for every wave
 };
 
-template <int NSR, int TW, int BH>
+template <int NSR, int TW, int BH, int CAPN>
 struct ScanLds : RunLds<NSR, TW, BH> {
     using G = Geo<NSR, TW, BH>;
     static constexpr bool GRAY = G::GRAY;
-    static constexpr int PRCAP = (int)(sizeof(ScanLate<NSR, TW, BH>) / 4);
+    static constexpr int PRCAP = (int)(sizeof(ScanLate<NSR, TW, BH, CAPN>) / 4);
     static constexpr int GN = GRAY ? G::NM : 1;
-    int32_t P[G::RCAP];     // parent array over nodes; later the key of each component
-    uint16_t SP[G::RCAP];   // start of each node: block row * TW + column
+    static_assert(CAPN % 32 == 0 && CAPN <= G::RCAP, "node capacity");
+    int32_t P[CAPN];        // parent array over nodes; later the key of each component
+    uint16_t SP[CAPN];      // start of each node: block row * TW + column
     // gray levels, bit per pixel: same value as the left neighbour (GE), as
     // the pixel above (GV), above-left (GD1), above-right (GD2)
     uint32_t GE[GN], GV[GN], GD1[GN], GD2[GN];
     union {
         uint32_t PR[PRCAP];  // during the union step: touching node pairs (x | y << 16)
-        ScanLate<NSR, TW, BH> late;
+        ScanLate<NSR, TW, BH, CAPN> late;
         uint8_t BY[GRAY ? G::TH * TW : 1];  // gray levels: the tile's bytes, until the masks exist
     };
-    static_assert(!GRAY || sizeof(BY) <= sizeof(ScanLate<NSR, TW, BH>), "gray tile layout");
+    static_assert(!GRAY || sizeof(BY) <= sizeof(ScanLate<NSR, TW, BH, CAPN>), "gray tile layout");
 };
 
-// Eight waves per SIMD (four workgroups per CU, as the LDS allows): the
-// register allocator is held to the matching scalar-register budget.
-template <int NSR, int TW, int BH, int ORD>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_scan(Batch b) {
+// Scan of one tile by NT threads with LDS for CAPN nodes.  With COMPACT a
+// tile whose runs outnumber CAPN is not scanned: its node count is stored
+// as -1 (kOverflow) and k_tile_scan_rest scans it later.
+constexpr int32_t kOverflow = -1;
+template <int NSR, int TW, int BH, int ORD, int NT, int CAPN, bool COMPACT>
+__device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLds<NSR, TW, BH, CAPN> &t) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
-    constexpr int NT = kTileThreads;
     constexpr int MPT = (G::NM + NT - 1) / NT;
     constexpr int UPT = (G::NU + NT - 1) / NT;
     // threads per (block row, word) unit in the union step, and the bits each takes
@@ -559,8 +572,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     static_assert(NT < G::NU || NT % G::NU == 0, "unit count must divide the thread count");
     constexpr int NW = G::NW, TH = G::TH;
     constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
-    __shared__ ScanLds<NSR, TW, BH> t;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    using L = ScanLds<NSR, TW, BH, CAPN>;
+    constexpr int CW = CAPN / 32;   // words of the LDS node and component bitmasks
     const Img &im = find_img(b, tile, kTile);
     const int ti = tile - im.tile0;
     const int ty = ti / im.NTX, tx = ti % im.NTX;
@@ -644,6 +657,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     // 2. block runs, their ordinals and start positions (the starts serve
     // the canonical keys only)
     const int32_t n_runs = number_runs<NSR, TW, BH, NT>(t, t.GE);
+    if (COMPACT && n_runs > CAPN) {
+        if (tid == 0)
+            im.tcnt[ti * 4 + 0] = kOverflow;
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < (ORD == kCanonical ? UPT : 0); k++) {
         const int u = tid + k * NT;
@@ -793,8 +811,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             t.P[run_node(sR, bR, c)] = 4 * upper_node(c + d, wU, bU);
         } while (l);
     }
-    for (int r0 = 0; r0 < n_pairs; r0 += ScanLds<NSR, TW, BH>::PRCAP) {
-        const int r1 = r0 + ScanLds<NSR, TW, BH>::PRCAP;
+    for (int r0 = 0; r0 < n_pairs; r0 += L::PRCAP) {
+        const int r1 = r0 + L::PRCAP;
 #pragma unroll
         for (int k = 0; k < UPT2; k++) {
             int32_t idx = coff[k];
@@ -837,7 +855,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
         // Each lane steps its own union (one load pair and one CAS per step)
         // and takes its next pair as soon as the current union ends.
-        const int np = min(n_pairs - r0, ScanLds<NSR, TW, BH>::PRCAP);
+        const int np = min(n_pairs - r0, L::PRCAP);
         int q = tid;
         int32_t rx = 0, ry = 0;  // byte offsets of the two nodes
         if (q < np) {
@@ -874,7 +892,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         for (int r = tid; r < TH; r += NT)
             t.late.rowcnt[r] = 0;
     }
-    for (int i = tid; i < G::RW; i += NT)
+    for (int i = tid; i < CW; i += NT)
         t.late.RFB[i] = 0u;
     __syncthreads();
 
@@ -889,9 +907,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             root = find_root_store<WG>(t.P, k) == 4 * k;
         const uint64_t bal = __ballot(root);
         const int wd = (k0 + wave * 64) >> 5;
-        if (lane == 0 && wd < G::RW)
+        if (lane == 0 && wd < CW)
             t.late.RFB[wd] = (uint32_t)bal;
-        if (lane == 32 && wd + 1 < G::RW)
+        if (lane == 32 && wd + 1 < CW)
             t.late.RFB[wd + 1] = (uint32_t)(bal >> 32);
     }
     __syncthreads();
@@ -915,9 +933,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         if (ORD == kCanonical) {
             const uint64_t bal = __ballot(same_row);
             const int wd = (k0 + wave * 64) >> 5;
-            if (lane == 0 && wd < G::RW)
+            if (lane == 0 && wd < CW)
                 t.late.RRB[wd] = (uint32_t)bal;
-            if (lane == 32 && wd + 1 < G::RW)
+            if (lane == 32 && wd + 1 < CW)
                 t.late.RRB[wd + 1] = (uint32_t)(bal >> 32);
         }
     }
@@ -929,7 +947,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         for (int c = tid; c < n_comp; c += NT)
             t.P[c] = 0x7FFFFFFF;
     }
-    for (int i = tid; i < G::RW; i += NT)
+    for (int i = tid; i < CW; i += NT)
         t.late.RFB[i] = 0u;  // from here on: boundary components
     __syncthreads();
     for (int k = tid; k < (ORD == kCanonical ? n_runs : 0); k += NT) {
@@ -1085,6 +1103,63 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             if (GRAY)
                 gmask[G::NM + i] = ereg[k];
         }
+    }
+}
+
+// Full form: eight waves per tile and per SIMD (four workgroups per CU, as
+// the LDS for every possible node allows); the register allocator is held
+// to the matching scalar-register budget.
+template <int NSR, int TW, int BH, int ORD>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_scan(Batch b) {
+    constexpr int C = Geo<NSR, TW, BH>::RCAP;
+    __shared__ ScanLds<NSR, TW, BH, C> t;
+    scan_tile<NSR, TW, BH, ORD, kTileThreads, C, false>(b, xcd_tile(blockIdx.x, gridDim.x), t);
+}
+
+// Compact form: four waves per tile, each lane taking a whole (block row,
+// word) unit, with LDS for compact_cap() nodes, so that six tiles share a
+// CU.  Fewer waves per tile issue fewer instructions for the same tile (the
+// per-wave work of each step is paid by half as many waves).
+constexpr int kScanThreadsC = 256;
+template <int NSR, int TW, int BH, int ORD>
+__global__ __launch_bounds__(kScanThreadsC) __attribute__((amdgpu_waves_per_eu(6))) void k_tile_scan_c(Batch b) {
+    constexpr int C = compact_cap<NSR, TW, BH>();
+    __shared__ ScanLds<NSR, TW, BH, C> t;
+    scan_tile<NSR, TW, BH, ORD, kScanThreadsC, C, true>(b, xcd_tile(blockIdx.x, gridDim.x), t);
+}
+
+// The tiles the compact form left (node count kOverflow), scanned by the
+// full form.  Workgroup g checks the node counts of a stretch of at most 64
+// consecutive tiles (the host launches at least ntiles / 64 workgroups) and
+// scans the marked ones one after another; with none marked it ends at once.
+template <int NSR, int TW, int BH, int ORD>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_tile_scan_rest(Batch b,
+                                                                                                       int32_t ntiles) {
+    constexpr int C = Geo<NSR, TW, BH>::RCAP;
+    __shared__ ScanLds<NSR, TW, BH, C> t;
+    __shared__ uint64_t marked;
+    const int32_t per = (ntiles + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+    const int32_t first = (int32_t)blockIdx.x * per;
+    if (first >= ntiles)
+        return;
+    if (threadIdx.x < 64) {
+        const int32_t tile = first + (int32_t)threadIdx.x;
+        bool m = false;
+        if ((int32_t)threadIdx.x < per && tile < ntiles) {
+            const Img &im = find_img(b, tile, kTile);
+            m = im.tcnt[(tile - im.tile0) * 4] == kOverflow;
+        }
+        const uint64_t bal = __ballot(m);
+        if (threadIdx.x == 0)
+            marked = bal;
+    }
+    __syncthreads();
+    uint64_t bits = marked;
+    while (bits) {
+        const int i = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1;
+        scan_tile<NSR, TW, BH, ORD, kTileThreads, C, false>(b, first + i, t);
+        __syncthreads();
     }
 }
 

@@ -107,6 +107,36 @@ def test_adversarial_medium(ccl, name):
         check(ccl, img, conn, what=name)
 
 
+def _dense_run_mix(H, W, seed):
+    """Noise with vertical 1-px stripes in some tile-sized blocks: tiles whose
+    run count exceeds the compact scan's node capacity (stripes: every other
+    column starts a run in every row) beside tiles it holds (noise), so that
+    both tile-scan forms write tables of one image and the merge joins them."""
+    img = inputs.bernoulli(H, W, 0.5, seed=seed, device=DEV)
+    cols = torch.arange(W, device=DEV)
+    stripe = ((cols % 2) == 0).to(torch.uint8)
+    for (r0, c0) in ((0, 0), (64, 256), (128, 700), (200, 1400), (320, 128)):
+        img[r0:r0 + 96, c0:c0 + 300] = stripe[c0:c0 + 300]
+    # a stripe block with a noise row through it joins the stripes together
+    img[150, :] = 1
+    return img
+
+
+def test_compact_and_full_tile_scans_in_one_image(ccl):
+    img = _dense_run_mix(420, 1777, 21)
+    for conn in (8, 4):
+        for tile in (0, 1, 4, 5, 7):
+            check(ccl, img, conn, tile=tile, what=f"stripes+noise tile {tile}")
+    # a checkerboard block: 4-connectivity makes every pixel a run
+    img2 = inputs.bernoulli(333, 999, 0.45, seed=22, device=DEV)
+    rr = torch.arange(333, device=DEV)[:, None]
+    cc = torch.arange(999, device=DEV)[None, :]
+    board = (((rr + cc) % 2) == 0).to(torch.uint8)
+    img2[40:200, 100:700] = board[40:200, 100:700]
+    for conn in (4, 8):
+        check(ccl, img2, conn, what="checkerboard block in noise")
+
+
 def test_strided_unaligned_and_odd_width(ccl):
     base = inputs.bernoulli(300, 1100, 0.5, seed=9, device=DEV)
     view = base[:, 3:1000]  # 3-byte offset: unaligned rows, stride 1100, W = 997
