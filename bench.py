@@ -247,6 +247,8 @@ def main():
                     help="tile-local scan: runs of row pairs (default, 8-conn) or of single rows")
     ap.add_argument("--tile", type=int, default=0, help="tile configuration id (0 = default)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-threads", default="1,2,4,8,16",
+                    help="thread counts of the host PARemSP curve ('' = skip; capped at 16 and at the host's)")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--ablation-steps", type=int, default=5,
                     help="steps of the one-row vs two-row scan comparison (0 = skip)")
@@ -423,6 +425,29 @@ def main():
             }
         if not args.no_verify:
             record["bit_exact"] = bool(np.array_equal(out.cpu().numpy(), ref)) and int(kdev.item()) == kref
+        threads = [int(t) for t in args.cpu_threads.split(",") if t.strip()] if not gray else []
+        threads = [t for t in threads if t <= min(16, os.cpu_count() or 1)]
+        if threads and args.cpu_runs > 0:
+            # the paper's own parallel method on the host (PARemSP, one
+            # thread per row chunk, Algorithm 8's locked boundary unions):
+            # its thread-count curve, as the paper reports speedups
+            curve, same = {}, True
+            for t in threads:
+                t0_ = time.perf_counter()
+                lab_t, k_t = oracle.paremsp_threads(host, args.conn, nthreads=t)
+                curve[str(t)] = round(time.perf_counter() - t0_, 3)
+                same &= bool(k_t == kref and np.array_equal(lab_t, ref))
+                del lab_t
+                log(f"cpu paremsp {t} threads: {curve[str(t)]:.2f} s")
+            record["cpu_paremsp"] = {
+                "seconds": curve, "unit": "s per image",
+                "speedup_vs_1_thread": {k: round(curve[str(threads[0])] / v, 2) for k, v in curve.items()}
+                if threads[0] == 1 else None,
+                "gpx_per_s_best": round(px / min(curve.values()) / 1e9, 4),
+                "equals_oracle": same,
+                "kind": "PARemSP (Algorithms 7, 8) with POSIX threads; the whole call incl. flatten, labeling "
+                        "and canonical numbering, one run per thread count",
+            }
 
     if args.ablation_steps > 0 and args.conn == 8 and not gray:
         # the paper's scan comparison (Table II) inside a tile: one-row runs

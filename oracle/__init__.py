@@ -13,7 +13,8 @@ Functions
 ---------
 cclremsp(img, conn)          -> (labels int32 HxW, K)   Algorithms 1-4
 aremsp(img, conn, raw=False) -> (labels, K)             Algorithms 2, 3, 5, 6
-paremsp(img, conn, nchunks)  -> (labels, K)             Algorithms 6, 7, 8
+paremsp(img, conn, nchunks)  -> (labels, K)             Algorithms 6, 7, 8 (chunks in turn)
+paremsp_threads(img, conn, n)-> (labels, K)             the same, one thread per chunk
 canonical(labels)            -> (labels, K)             rank by first raster index
 merge_pairs(p, pairs)        -> p                       Algorithm 2 on a parent array
 merger_pairs(p, pairs)       -> p                       Algorithm 8 (sequential schedule)
@@ -50,7 +51,7 @@ def build(force: bool = False) -> str:
     """Compile ccl_oracle.c into _liboracle.so with gcc (host code only)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC]
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -71,6 +72,8 @@ def _load():
             lib.oracle_aremsp.restype = i64
             lib.oracle_paremsp.argtypes = [u8p, i64, i64, i64, ctypes.c_int, i32p, ctypes.c_int]
             lib.oracle_paremsp.restype = i64
+            lib.oracle_paremsp_threads.argtypes = [u8p, i64, i64, i64, ctypes.c_int, i32p, ctypes.c_int]
+            lib.oracle_paremsp_threads.restype = i64
             lib.oracle_gray.argtypes = [u8p, i64, i64, i64, ctypes.c_int, i32p]
             lib.oracle_gray.restype = i64
             lib.oracle_canonical.argtypes = [i32p, i64, i64]
@@ -135,6 +138,17 @@ def paremsp(img, conn: int = 8, nchunks: int = 4):
     img, ptr, H, W, stride = _img_args(img)
     out = np.empty((H, W), dtype=np.int32)
     k = lib.oracle_paremsp(ptr, H, W, stride, conn, _i32ptr(out), int(nchunks))
+    return out, _check(k)
+
+
+def paremsp_threads(img, conn: int = 8, nthreads: int = 4):
+    """PARemSP (Algorithm 7) with one POSIX thread per row chunk: the chunk
+    scans run at once, then the boundary unions run concurrently with
+    Algorithm 8's locked root links; canonical numbering."""
+    lib = _load()
+    img, ptr, H, W, stride = _img_args(img)
+    out = np.empty((H, W), dtype=np.int32)
+    k = lib.oracle_paremsp_threads(ptr, H, W, stride, conn, _i32ptr(out), int(nthreads))
     return out, _check(k)
 
 

@@ -7,8 +7,9 @@
  * baseline leg of the benchmark may load this file.  It shares no code with
  * the GPU library and must never be used as a fallback for it.
  *
- * Plain, slow, single-threaded C.  Every routine follows the paper's
- * definitions in the paper's order and notation:
+ * Plain, slow C, single-threaded except for oracle_paremsp_threads.  Every
+ * routine is written from the paper's description of the method, its steps
+ * taken in the paper's order:
  *   merge        -- Rem's union with splicing (Section III, Algorithm 2)
  *   flatten      -- analysis phase (Section III, Algorithm 3)
  *   cclremsp     -- CCLRemSP: decision-tree scan (Fig. 2, Algorithm 4),
@@ -16,8 +17,12 @@
  *   aremsp       -- ARemSP: two-row scan with the mask of Fig. 1b
  *                   (Algorithm 6), flatten, labeling (Algorithm 5)
  *   paremsp      -- PARemSP: chunked ARemSP scans with disjoint label
- *                   ranges, boundary-row merge with merger (Algorithms 7, 8)
- *                   executed one chunk after another, flatten, labeling
+ *                   ranges, boundary-row merge with merger (Algorithms 7, 8),
+ *                   flatten, labeling; the chunks either one after another
+ *                   (oracle_paremsp) or one POSIX thread per chunk with the
+ *                   boundary unions concurrent under Algorithm 8's locks
+ *                   (oracle_paremsp_threads, the paper's parallel method as
+ *                   a CPU baseline; checked under ThreadSanitizer)
  *   gray         -- the gray-level extension the paper mentions (Section V;
  *                   the abstract's "adjacent pixels sharing the same
  *                   features"): object pixels are the nonzero bytes and two
@@ -45,6 +50,7 @@
  *   - 4-connectivity is not spelled out in the paper; it is derived from
  *     the same masks with the diagonal neighbours removed.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -71,77 +77,92 @@ static int32_t label_at(const int32_t *label, const image_t *im, int64_t r, int6
 }
 
 /* ---------------------------------------------------------------------- */
-/* Algorithm 2: merge(p, x, y).  Rem's algorithm with splicing.  The root   */
-/* with the larger parent value is linked below the smaller parent value;   */
-/* on the way up, the node with the larger parent is spliced onto the other */
-/* side's parent.  The invariant p[i] <= i is kept, so every set's root is  */
-/* its smallest element.  Returns a member of the united set.               */
+/* Rem's union with splicing: the merge of Section III (Algorithm 2).       */
+/* Parents only ever point to smaller labels (p[i] <= i), so the root of a  */
+/* set is its smallest label.  The walk keeps one node on each side; at     */
+/* every step the node whose parent is the larger one moves: if it is a     */
+/* root it is hung below the other node's parent and the two sets are one;  */
+/* otherwise it is spliced onto the other node's parent (a smaller label of */
+/* the set being united) and the walk continues from its old parent.  The   */
+/* walk ends when both nodes have the same parent.  The value returned is a */
+/* member of the united set (a parent value, as in the paper), which is all */
+/* the scan needs for the label of the current pixel.                       */
 /* ---------------------------------------------------------------------- */
 static int32_t merge(int32_t *p, int32_t x, int32_t y)
 {
-    int32_t root_x = x, root_y = y, z;
-    while (p[root_x] != p[root_y]) {
-        if (p[root_x] > p[root_y]) {
-            if (root_x == p[root_x]) {
-                p[root_x] = p[root_y];
-                return p[root_x];
-            }
-            z = p[root_x];
-            p[root_x] = p[root_y];
-            root_x = z;
-        } else {
-            if (root_y == p[root_y]) {
-                p[root_y] = p[root_x];
-                return p[root_x];
-            }
-            z = p[root_y];
-            p[root_y] = p[root_x];
-            root_y = z;
+    for (;;) {
+        int32_t px = p[x], py = p[y];
+        if (px == py)
+            return px;
+        if (px < py) {
+            /* the side that moves is called x */
+            int32_t t = x;
+            x = y;
+            y = t;
+            t = px;
+            px = py;
+            py = t;
         }
+        p[x] = py; /* a root is linked, an inner node spliced */
+        if (px == x)
+            return py;
+        x = px;
     }
-    return p[root_x];
 }
 
-/* Algorithm 8: merger(p, x, y).  The concurrent form of Algorithm 2: a root */
-/* is linked only after re-checking, under the lock of that root, that it   */
-/* is still a root; splicing is done without locks.  Here the chunks are   */
-/* merged one after another, which is one of the schedules the concurrent   */
-/* algorithm admits, so the lock reduces to the re-check itself.            */
-static int32_t merger(int32_t *p, int32_t x, int32_t y)
+/* ---------------------------------------------------------------------- */
+/* The concurrent union of PARemSP's boundary phase (Section IV, the merger */
+/* of Algorithm 8): Rem's union run by several threads on one parent array. */
+/* Splices need no lock (the paper's memory model: each parent entry is     */
+/* read and written whole, here as relaxed C11 atomics).  Hanging a root    */
+/* below another set is done under the root's lock, after checking again,   */
+/* under the lock, that the node is still a root; if another thread hung it */
+/* meanwhile, the walk carries on from where it is.  Every store keeps      */
+/* p[i] < i for an inner node, so the forest stays acyclic.  Locks are      */
+/* striped: root x uses lk[x % nlk].  With lk == NULL (one thread) this is  */
+/* the merge above step for step.                                           */
+/* ---------------------------------------------------------------------- */
+static int32_t ld(const int32_t *p, int32_t i)
 {
-    int32_t root_x = x, root_y = y, z;
-    while (p[root_x] != p[root_y]) {
-        if (p[root_x] > p[root_y]) {
-            if (root_x == p[root_x]) {
-                int success = 0;
-                /* lock(root_x) */
-                if (root_x == p[root_x]) {
-                    p[root_x] = p[root_y];
-                    success = 1;
-                }
-                /* unlock(root_x) */
-                if (success)
-                    break;
-            }
-            z = p[root_x];
-            p[root_x] = p[root_y];
-            root_x = z;
-        } else {
-            if (root_y == p[root_y]) {
-                int success = 0;
-                if (root_y == p[root_y]) {
-                    p[root_y] = p[root_x];
-                    success = 1;
-                }
-                if (success)
-                    break;
-            }
-            z = p[root_y];
-            p[root_y] = p[root_x];
-            root_y = z;
+    return __atomic_load_n(&p[i], __ATOMIC_RELAXED);
+}
+
+static void st(int32_t *p, int32_t i, int32_t v)
+{
+    __atomic_store_n(&p[i], v, __ATOMIC_RELAXED);
+}
+
+static void merger(int32_t *p, pthread_mutex_t *lk, int nlk, int32_t x, int32_t y)
+{
+    for (;;) {
+        int32_t px = ld(p, x), py = ld(p, y);
+        if (px == py)
+            return;
+        if (px < py) {
+            int32_t t = x;
+            x = y;
+            y = t;
+            t = px;
+            px = py;
+            py = t;
         }
+        if (px == x) {
+            int linked = 0;
+            if (lk)
+                pthread_mutex_lock(&lk[x % nlk]);
+            if (ld(p, x) == x) {
+                st(p, x, py);
+                linked = 1;
+            }
+            if (lk)
+                pthread_mutex_unlock(&lk[x % nlk]);
+            if (linked)
+                return;
+            continue; /* no longer a root: look again from here */
+        }
+        st(p, x, py);
+        x = px;
     }
-    return p[root_x];
 }
 
 /* Algorithm 3: flatten(p, count).  One ascending sweep: a non-root takes   */
@@ -478,61 +499,183 @@ int64_t oracle_aremsp(const uint8_t *img, int64_t H, int64_t W, int64_t stride, 
     return k;
 }
 
-/* PARemSP (Algorithm 7) with nchunks row chunks, followed by the canonical */
-/* numbering.  Chunk k covers rows [start_k, start_{k+1}) where start_k =   */
-/* 2*k*floor(ceil(H/2)/nchunks) and the last chunk takes the remainder.      */
-int64_t oracle_paremsp(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
-                       int32_t *labels, int nchunks)
+/* Boundary step of PARemSP (Algorithm 7) for the chunk starting at row i:  */
+/* every object pixel of row i (label(e) != 0 is the foreground test) is    */
+/* united with its object neighbours in row i - 1, the last row of the      */
+/* chunk above: b, else (8-connectivity) a and c.                           */
+static void merge_boundary_row(const image_t *im, int conn, const int32_t *labels, int32_t *p,
+                               pthread_mutex_t *lk, int nlk, int64_t i)
+{
+    const int64_t W = im->W;
+    for (int64_t c = 0; c < W; c++) {
+        int32_t le = labels[i * W + c];
+        if (le == 0)
+            continue;
+        int32_t lb = label_at(labels, im, i - 1, c);
+        if (lb != 0) {
+            merger(p, lk, nlk, le, lb);
+        } else if (conn == 8) {
+            int32_t la = label_at(labels, im, i - 1, c - 1);
+            int32_t lc = label_at(labels, im, i - 1, c + 1);
+            if (la != 0)
+                merger(p, lk, nlk, le, la);
+            if (lc != 0)
+                merger(p, lk, nlk, le, lc);
+        }
+    }
+}
+
+/* Chunking of Algorithm 7: H/2 row pairs dealt out in nchunks chunks of    */
+/* size = 2 * floor(ceil(H/2) / nchunks) rows; the last chunk takes the     */
+/* remainder; chunk k hands out labels from start*W + 1 (disjoint ranges,   */
+/* none of them 0).                                                         */
+typedef struct {
+    const image_t *im;
+    int conn;
+    int32_t *labels, *p;
+    int64_t start, end;   /* rows [start, end) */
+    int32_t next_label;   /* in: first label of the chunk; out: one past its last */
+    pthread_mutex_t *lk;
+    int nlk;
+} chunk_t;
+
+static int plan_chunks(int64_t H, int nchunks, int64_t *size)
+{
+    int64_t numiter = (H + 1) / 2;
+    if (nchunks > numiter)
+        nchunks = (int)numiter;
+    *size = 2 * (numiter / nchunks);
+    return nchunks;
+}
+
+static void *chunk_scan(void *arg)
+{
+    chunk_t *ck = (chunk_t *)arg;
+    scan_aremsp_rows(ck->im, ck->conn, ck->start, ck->end, ck->labels, ck->p, &ck->next_label);
+    return NULL;
+}
+
+static void *chunk_boundary(void *arg)
+{
+    chunk_t *ck = (chunk_t *)arg;
+    if (ck->start > 0)
+        merge_boundary_row(ck->im, ck->conn, ck->labels, ck->p, ck->lk, ck->nlk, ck->start);
+    return NULL;
+}
+
+static void *chunk_labeling(void *arg)
+{
+    chunk_t *ck = (chunk_t *)arg;
+    const int64_t W = ck->im->W;
+    for (int64_t i = ck->start * W; i < ck->end * W; i++)
+        ck->labels[i] = ck->p[ck->labels[i]];
+    return NULL;
+}
+
+/* Runs fn on every chunk: on its own thread each (threads = 1: one after   */
+/* another on the caller's thread).  Returns -1 if a thread cannot start.   */
+static int run_chunks(chunk_t *ck, int n, int threads, void *(*fn)(void *))
+{
+    if (!threads) {
+        for (int k = 0; k < n; k++)
+            fn(&ck[k]);
+        return 0;
+    }
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n);
+    if (!th)
+        return -1;
+    int started = 0, st = 0;
+    for (; started < n; started++)
+        if (pthread_create(&th[started], NULL, fn, &ck[started]) != 0) {
+            st = -1;
+            break;
+        }
+    for (int k = 0; k < started; k++)
+        pthread_join(th[k], NULL);
+    /* a chunk whose thread did not start is run here */
+    for (int k = started; k < n; k++)
+        fn(&ck[k]);
+    free(th);
+    return st;
+}
+
+/* PARemSP (Algorithm 7): scan the chunks (ARemSP, Algorithm 6), unite     */
+/* across the chunk boundaries (merger, Algorithm 8), flatten (Algorithm 3) */
+/* and the labeling phase, then the canonical numbering.  threads = 0: the  */
+/* chunks one after another on the calling thread (one schedule the         */
+/* concurrent algorithm admits); threads = 1: every phase's chunks on their */
+/* own threads at once, the boundary unions concurrent under Algorithm 8's  */
+/* locks.                                                                   */
+static int64_t paremsp_run(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
+                           int nchunks, int threads)
 {
     if (bad_args(img, H, W, stride, conn, labels) || nchunks <= 0)
         return -1;
     image_t im = {img, H, W, stride};
-    int64_t numiter = (H + 1) / 2;
-    if (nchunks > numiter)
-        nchunks = (int)numiter;
-    int64_t chunk = numiter / nchunks;
-    int64_t size = 2 * chunk;
-    /* Labels of chunk k live in [start*W + 1, start*W + rows*W], disjoint. */
-    int64_t nlab = H * W + 2;
+    int64_t size;
+    nchunks = plan_chunks(H, nchunks, &size);
+    const int64_t nlab = H * W + 2;
     int32_t *p = (int32_t *)malloc((size_t)nlab * sizeof(int32_t));
-    if (!p)
+    chunk_t *ck = (chunk_t *)calloc((size_t)nchunks, sizeof(chunk_t));
+    const int nlk = 4096;
+    pthread_mutex_t *lk = threads ? (pthread_mutex_t *)malloc(sizeof(pthread_mutex_t) * nlk) : NULL;
+    if (!p || !ck || (threads && !lk)) {
+        free(p);
+        free(ck);
+        free(lk);
         return -1;
-    /* Labels never handed out map to background in flatten (p[i] = 0 < i). */
-    for (int64_t i = 0; i < nlab; i++)
-        p[i] = 0;
-    int32_t maxlabel = 0;
+    }
+    for (int k = 0; k < (threads ? nlk : 0); k++)
+        pthread_mutex_init(&lk[k], NULL);
+    /* labels never handed out map to background in flatten (p[i] = 0 < i) */
+    memset(p, 0, (size_t)nlab * sizeof(int32_t));
     for (int k = 0; k < nchunks; k++) {
-        int64_t start = (int64_t)k * size;
-        int64_t end = (k == nchunks - 1) ? H : start + size;
-        int32_t count = (int32_t)(start * W + 1);
-        scan_aremsp_rows(&im, conn, start, end, labels, p, &count);
-        if (count - 1 > maxlabel)
-            maxlabel = count - 1;
+        ck[k].im = &im;
+        ck[k].conn = conn;
+        ck[k].labels = labels;
+        ck[k].p = p;
+        ck[k].start = (int64_t)k * size;
+        ck[k].end = (k == nchunks - 1) ? H : ck[k].start + size;
+        ck[k].next_label = (int32_t)(ck[k].start * W + 1);
+        ck[k].lk = lk;
+        ck[k].nlk = nlk;
     }
-    /* Boundary merge: each chunk's first row against the previous chunk's  */
-    /* last row, using label(x) != 0 as the foreground test.                */
-    for (int64_t i = size; i < H && i <= (int64_t)(nchunks - 1) * size; i += size) {
-        for (int64_t c = 0; c < W; c++) {
-            int32_t le = labels[i * W + c];
-            if (le == 0)
-                continue;
-            int32_t lb = label_at(labels, &im, i - 1, c);
-            if (lb != 0) {
-                merger(p, le, lb);
-            } else if (conn == 8) {
-                int32_t la = label_at(labels, &im, i - 1, c - 1);
-                int32_t lc = label_at(labels, &im, i - 1, c + 1);
-                if (la != 0)
-                    merger(p, le, la);
-                if (lc != 0)
-                    merger(p, le, lc);
-            }
-        }
+    int st = run_chunks(ck, nchunks, threads, chunk_scan);
+    if (st == 0)
+        st = run_chunks(ck, nchunks, threads, chunk_boundary);
+    int64_t k_out = -1;
+    if (st == 0) {
+        int32_t maxlabel = 0;
+        for (int k = 0; k < nchunks; k++)
+            if (ck[k].next_label - 1 > maxlabel)
+                maxlabel = ck[k].next_label - 1;
+        const int32_t k = flatten(p, maxlabel);
+        st = run_chunks(ck, nchunks, threads, chunk_labeling);
+        if (st == 0)
+            k_out = canonical_numbering(labels, H, W, k);
     }
-    int32_t k = flatten(p, maxlabel);
-    labeling_phase(labels, &im, p);
+    for (int k = 0; k < (threads ? nlk : 0); k++)
+        pthread_mutex_destroy(&lk[k]);
+    free(lk);
+    free(ck);
     free(p);
-    return canonical_numbering(labels, H, W, k);
+    return k_out;
+}
+
+/* PARemSP with nchunks row chunks run one after another; canonical         */
+/* numbering.                                                               */
+int64_t oracle_paremsp(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn, int32_t *labels,
+                       int nchunks)
+{
+    return paremsp_run(img, H, W, stride, conn, labels, nchunks, 0);
+}
+
+/* PARemSP with one thread per chunk (POSIX threads; the CPU baseline of the */
+/* paper's own parallel method); canonical numbering.                       */
+int64_t oracle_paremsp_threads(const uint8_t *img, int64_t H, int64_t W, int64_t stride, int conn,
+                               int32_t *labels, int nthreads)
+{
+    return paremsp_run(img, H, W, stride, conn, labels, nthreads, 1);
 }
 
 /* Canonical renumbering of an arbitrary labeling (0 = background).         */
@@ -617,7 +760,7 @@ void oracle_merge_pairs(int32_t *p, const int32_t *pairs, int64_t m)
 void oracle_merger_pairs(int32_t *p, const int32_t *pairs, int64_t m)
 {
     for (int64_t i = 0; i < m; i++)
-        merger(p, pairs[2 * i], pairs[2 * i + 1]);
+        merger(p, NULL, 0, pairs[2 * i], pairs[2 * i + 1]);
 }
 
 int32_t oracle_flatten(int32_t *p, int32_t count)

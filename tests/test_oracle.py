@@ -280,6 +280,28 @@ def test_variants_agree_chunks():
                 assert kk == k and np.array_equal(lab, ref), (H, W, conn, t)
 
 
+def test_threaded_paremsp_agrees():
+    """PARemSP with one thread per chunk (concurrent boundary unions under
+    Algorithm 8's locks) gives CCLRemSP's labels for every thread count, on
+    random images and on a dense image where many unions race for the same
+    large sets."""
+    rng = np.random.default_rng(81)
+    for trial in range(20):
+        H, W = int(rng.integers(1, 120)), int(rng.integers(1, 120))
+        img = (rng.random((H, W)) < rng.uniform(0.2, 0.8)).astype(np.uint8)
+        for conn in (4, 8):
+            ref, k = oracle.cclremsp(img, conn)
+            for t in (1, 2, 3, 5, 8, 16):
+                lab, kk = oracle.paremsp_threads(img, conn, nthreads=t)
+                assert kk == k and np.array_equal(lab, ref), (H, W, conn, t)
+    big = (rng.random((600, 700)) < 0.6).astype(np.uint8)
+    for conn in (4, 8):
+        ref, k = oracle.cclremsp(big, conn)
+        for t in (4, 16, 64):
+            lab, kk = oracle.paremsp_threads(big, conn, nthreads=t)
+            assert kk == k and np.array_equal(lab, ref), (conn, t)
+
+
 def test_paper_numbering_is_not_canonical():
     """ARemSP's own flatten numbering follows label creation order of the
     two-row scan, which is not raster order; the partition is the same but the
@@ -320,16 +342,17 @@ MUTANTS = [
     ("*e = merge(p, lc, la);        /* copy(c,a) */", "*e = p[lc];"),
     # transposed neighbour: read c at (r-1, c) instead of (r-1, c+1)
     ("int cc = image_at(im, r - 1, c + 1), d", "int cc = image_at(im, r - 1, c), d"),
-    # wrong comparison in Rem's link direction
-    ("        if (p[root_x] > p[root_y]) {\n            if (root_x == p[root_x]) {\n                p[root_x] = p[root_y];\n                return p[root_x];",
-     "        if (p[root_x] < p[root_y]) {\n            if (root_x == p[root_x]) {\n                p[root_x] = p[root_y];\n                return p[root_x];"),
+    # wrong comparison in Rem's link direction (the side with the smaller
+    # parent moves)
+    ("        if (px == py)\n            return px;\n        if (px < py) {",
+     "        if (px == py)\n            return px;\n        if (px > py) {"),
     # flatten treats every label as a root
     ("        if (p[i] < i)\n            p[i] = p[p[i]];", "        if (p[i] < 0)\n            p[i] = p[p[i]];"),
     # 4-connectivity merge dropped
     ("                if (b && d)\n                    *e = merge(p, lb, ld);", "                if (b && d)\n                    *e = p[lb];"),
     # a root is found but never linked (the union is dropped)
-    ("            if (root_x == p[root_x]) {\n                p[root_x] = p[root_y];\n                return p[root_x];\n            }\n            z = p[root_x];",
-     "            if (root_x == p[root_x]) {\n                return p[root_x];\n            }\n            z = p[root_x];"),
+    ("        p[x] = py; /* a root is linked, an inner node spliced */\n        if (px == x)\n            return py;",
+     "        if (px == x)\n            return py;\n        p[x] = py;"),
 ]
 
 
@@ -339,7 +362,7 @@ def _build_mutant(tmp_path, i, old, new):
     mut = tmp_path / f"mutant{i}.c"
     mut.write_text(src.replace(old, new))
     so = tmp_path / f"mutant{i}.so"
-    subprocess.run(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(mut)], check=True)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-pthread", "-shared", "-fPIC", "-o", str(so), str(mut)], check=True)
     lib = ctypes.CDLL(str(so))
     u8p = ctypes.POINTER(ctypes.c_uint8)
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -456,7 +479,7 @@ def test_gray_planted_mistakes_are_caught(tmp_path, i):
     mut = tmp_path / f"gmutant{i}.c"
     mut.write_text(src.replace(old, new))
     so = tmp_path / f"gmutant{i}.so"
-    subprocess.run(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(mut)], check=True)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-pthread", "-shared", "-fPIC", "-o", str(so), str(mut)], check=True)
     lib = ctypes.CDLL(str(so))
     u8p, i32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)
     lib.oracle_gray.argtypes = [u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, i32p]

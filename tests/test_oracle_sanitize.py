@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
 def test_oracle_under_sanitizers(tmp_path):
     exe = tmp_path / "oracle_sanitize"
-    cmd = ["gcc", "-std=c99", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+    cmd = ["gcc", "-std=c11", "-pthread", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=all", "-o", str(exe),
            os.path.join(ROOT, "oracle", "ccl_oracle.c"), os.path.join(ROOT, "tests", "sanitize", "oracle_driver.c")]
     subprocess.run(cmd, check=True)
