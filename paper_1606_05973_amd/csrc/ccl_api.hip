@@ -57,6 +57,18 @@ inline int tile_id_of(const Desc &d, int call_tile) {
     return t ? t : kDefaultTile[kind_of(d)];
 }
 
+// Labeling-pass store form an image allows: 16-byte stores need W % 4 == 0
+// and 16-byte aligned labels; very wide rows need the any-width form.  A
+// group takes the most general form any of its images needs.
+int store_form(const Desc &d) {
+    static_assert(kStoreAny < kStore4 && kStore4 < kStore16, "store forms ordered from the most general");
+    if (d.W > kVecMaxW)
+        return kStoreAny;
+    if (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0)
+        return kStore4;
+    return kStore16;
+}
+
 // Images of one kind, output order and tile configuration share every
 // launch of a batch (one launch group).
 struct GroupKey {
@@ -66,6 +78,13 @@ struct GroupKey {
     }
 };
 inline GroupKey key_of(const Desc &d, int call_tile) { return {kind_of(d), d.order, tile_id_of(d, call_tile)}; }
+
+// Inside a launch group the images are ordered by labeling-pass store form
+// (16-byte, 4-byte, plain), so that each form's tiles form one range that a
+// labeling-pass launch of that form covers.
+constexpr int kForms = 3;
+constexpr int kFormOrder[kForms] = {kStore16, kStore4, kStoreAny};
+inline int form_rank(int form) { return form == kStore16 ? 0 : (form == kStore4 ? 1 : 2); }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
@@ -390,7 +409,8 @@ int persistent_groups(int threads) {
 }
 
 template <int NSR, int TW, int BH, int ORD>
-int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg, hipStream_t s, bool marks) {
+int launch_all(const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t edges, int64_t blocks, int nimg,
+               hipStream_t s, bool marks) {
     if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
         return CCL_ERR_TOO_LARGE;
     const dim3 blk(kThreads);
@@ -427,27 +447,35 @@ int launch_all(const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int
     else
         hipLaunchKernelGGL((k_comp_labels_prov<NSR, TW, BH>), tile_groups, blk, 0, s, b, (int32_t)tiles);
     pm.mark();
-#define CCL_RELABEL(F_)                                                                                     \
-    hipLaunchKernelGGL((k_relabel<NSR, TW, BH, F_>),                                                        \
-                       dim3((uint32_t)std::min<int64_t>(tiles, persistent_groups<k_relabel<NSR, TW, BH, F_>>(kTileThreads))), \
-                       dim3(kTileThreads), 0, s, b, (int32_t)tiles)
-    if (b.store == kStore16)
-        CCL_RELABEL(kStore16);
-    else if (b.store == kStore4)
-        CCL_RELABEL(kStore4);
-    else
-        CCL_RELABEL(kStoreAny);
+    // one labeling-pass launch per store form, over that form's tile range
+    int64_t tbeg = 0;
+    for (int f = 0; f < kForms; f++) {
+        const int64_t nt = form_tiles[f];
+        if (nt <= 0)
+            continue;
+#define CCL_RELABEL(F_)                                                                                       \
+    hipLaunchKernelGGL((k_relabel<NSR, TW, BH, F_>),                                                          \
+                       dim3((uint32_t)std::min<int64_t>(nt, persistent_groups<k_relabel<NSR, TW, BH, F_>>(kTileThreads))), \
+                       dim3(kTileThreads), 0, s, b, (int32_t)tbeg, (int32_t)nt)
+        if (kFormOrder[f] == kStore16)
+            CCL_RELABEL(kStore16);
+        else if (kFormOrder[f] == kStore4)
+            CCL_RELABEL(kStore4);
+        else
+            CCL_RELABEL(kStoreAny);
 #undef CCL_RELABEL
+        tbeg += nt;
+    }
     pm.mark();
     return hipGetLastError() == hipSuccess ? CCL_OK : CCL_ERR_HIP;
 }
 
-int dispatch(const GroupKey &g, const Batch &b, int64_t tiles, int64_t edges, int64_t blocks, int nimg,
-             hipStream_t s, bool marks = true) {
+int dispatch(const GroupKey &g, const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t edges,
+             int64_t blocks, int nimg, hipStream_t s, bool marks = true) {
     const TileCfg &c = kTiles[g.tile - 1];
 #define CCL_ORD(N_, W_, B_) \
-    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, edges, blocks, nimg, s, marks) \
-                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, edges, blocks, nimg, s, marks))
+    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, form_tiles, edges, blocks, nimg, s, marks) \
+                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, form_tiles, edges, blocks, nimg, s, marks))
 #define CCL_TILE_CASE(N_, W_)                                                                       \
     if (c.nsr == N_ && c.tw == W_)                                                                  \
         return g.kind == kPair ? CCL_ORD(N_, W_, 2) : g.kind == kRow ? CCL_ORD(N_, W_, 1) : CCL_ORD(N_, W_, 0);
@@ -490,6 +518,9 @@ Plan plan_batch(const Desc *descs, int n, int call_tile) {
     std::map<GroupKey, std::vector<int>> by;
     for (int i = 0; i < n; i++)
         by[key_of(descs[i], call_tile)].push_back(i);
+    for (auto &kv : by)
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [&](int a, int c) { return form_rank(store_form(descs[a])) < form_rank(store_form(descs[c])); });
     for (auto &kv : by) {
         P.keys.push_back(kv.first);
         P.tab_at.push_back(P.tables);
@@ -511,22 +542,11 @@ Plan plan_batch(const Desc *descs, int n, int call_tile) {
 
 size_t batch_bytes(const Desc *descs, int n, int call_tile) { return plan_batch(descs, n, call_tile).bytes; }
 
-// Labeling-pass store form an image allows: 16-byte stores need W % 4 == 0
-// and 16-byte aligned labels; very wide rows need the any-width form.  A
-// group takes the most general form any of its images needs.
-int store_form(const Desc &d) {
-    static_assert(kStoreAny < kStore4 && kStore4 < kStore16, "store forms ordered from the most general");
-    if (d.W > kVecMaxW)
-        return kStoreAny;
-    if (d.W % 4 != 0 || (reinterpret_cast<uintptr_t>(d.labels) & 15u) != 0)
-        return kStore4;
-    return kStore16;
-}
-
 // One group's launch arguments, its table written to `tab_bytes` (host).
 struct GroupRun {
     Batch b;
     int64_t tiles, edges, blocks;
+    int64_t form_tiles[kForms];   // tiles of the 16-byte, 4-byte and plain-store images, in that order
 };
 
 int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *tab_bytes, GroupRun *out) {
@@ -537,7 +557,7 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
     int64_t tiles = 0, edges = 0, blocks = 0;
     Batch b{};
     b.n = n;
-    b.store = kStore16;
+    int64_t form_tiles[kForms] = {0, 0, 0};
     for (int k = 0; k < n; k++) {
         const int i = idx[k];
         const Desc &d = descs[i];
@@ -553,7 +573,7 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
         blocks += P.lays[i].nblk;
         if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
             return CCL_ERR_TOO_LARGE;
-        b.store = std::min(b.store, store_form(d));
+        form_tiles[form_rank(store_form(d))] += P.lays[i].NT;
     }
     if (n == 1) {
         b.one = tab[0];
@@ -562,6 +582,8 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
         b.keys = reinterpret_cast<const int32_t *>(base + P.tab_at[g] + (size_t)n * sizeof(Img));
     }
     out->b = b;
+    for (int f = 0; f < kForms; f++)
+        out->form_tiles[f] = form_tiles[f];
     out->tiles = tiles;
     out->edges = edges;
     out->blocks = blocks;
@@ -582,8 +604,8 @@ int build_plan(const Desc *descs, const Plan &P, char *base, char *host, std::ve
 
 int launch_plan(const Plan &P, const std::vector<GroupRun> &runs, hipStream_t stream) {
     for (size_t g = 0; g < P.keys.size(); g++) {
-        const int st = dispatch(P.keys[g], runs[g].b, runs[g].tiles, runs[g].edges, runs[g].blocks,
-                                (int)P.members[g].size(), stream);
+        const int st = dispatch(P.keys[g], runs[g].b, runs[g].tiles, runs[g].form_tiles, runs[g].edges,
+                                runs[g].blocks, (int)P.members[g].size(), stream);
         if (st != CCL_OK)
             return st;
     }
@@ -716,9 +738,10 @@ int ccl_label_noalloc(const uint8_t *img, int64_t H, int64_t W, int64_t stride, 
     // a single image travels in the kernel arguments (no table upload)
     Batch b{};
     b.n = 1;
-    b.store = store_form(d);
     b.one = make_img(d, L, base + at);
-    return dispatch(g, b, L.NT, L.nedge, L.nblk, 1, stream, false);
+    int64_t form_tiles[kForms] = {0, 0, 0};
+    form_tiles[form_rank(store_form(d))] = L.NT;
+    return dispatch(g, b, L.NT, form_tiles, L.nedge, L.nblk, 1, stream, false);
 }
 
 int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream) {

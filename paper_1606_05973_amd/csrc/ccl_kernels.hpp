@@ -96,7 +96,6 @@ struct Batch {
     const int32_t *keys;    // n tile0, then n edge0, then n scan0 of the table (n > 1)
     Img one;                // the image when n == 1
     int32_t n;
-    int32_t store;   // labeling-pass store form (StoreForm) that suits every image
 };
 constexpr int32_t kVecMaxW = 1 << 22;  // keeps a tile's row offsets in bytes below 2^31
 
@@ -293,6 +292,27 @@ __device__ __forceinline__ uint32_t eq32(const uint32_t *a, const uint32_t *b) {
     return m;
 }
 
+// 32 bytes from a row address p that is not 16-byte aligned, as 8 dwords:
+// the nine aligned dwords that cover them are loaded (two 16-byte loads at
+// 4-byte alignment and one dword) and shifted into place with byte aligns.
+// The loaded dwords reach at most 3 bytes before p and after p + 31; an
+// aligned dword holding one byte of the image lies in a page of the image,
+// so those bytes are readable (and unused).
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ void load_unaligned32(const uint8_t *p, uint32_t *d) {
+    // (the aligned address by pointer arithmetic, so that the compiler keeps
+    // the global address space and emits global, not flat, loads)
+    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(p) & 3u);
+    const uint32_t *a = reinterpret_cast<const uint32_t *>(p - sh);
+    const u32x4a4 lo = __builtin_nontemporal_load(reinterpret_cast<const u32x4a4 *>(a));
+    const u32x4a4 hi = __builtin_nontemporal_load(reinterpret_cast<const u32x4a4 *>(a + 4));
+    const uint32_t w8 = sh ? a[8] : 0u;
+    const uint32_t w[9] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w, w8};
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+        d[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
+}
+
 // The 32 bytes of row y from column x (x % 32 == 0) as 8 dwords; bytes
 // outside the image read as 0.
 __device__ __forceinline__ void load_bytes(const Img &im, int y, int x, uint32_t *d) {
@@ -307,6 +327,10 @@ __device__ __forceinline__ void load_bytes(const Img &im, int y, int x, uint32_t
         const u32x4 b = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + 16));
         d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
         d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
+        return;
+    }
+    if (x + 32 <= im.W) {
+        load_unaligned32(p, d);
         return;
     }
     const int n = im.W - x < 32 ? im.W - x : 32;
@@ -351,6 +375,11 @@ __device__ __forceinline__ uint32_t load_word(const Img &im, int y, int x) {
         }
         const uint32_t k = (uint32_t)(255 - lv) * 0x01010101u;
         return gt16<true>(a, k) | (gt16<true>(b, k) << 16);
+    }
+    if (x + 32 <= im.W) {
+        uint32_t d[8];
+        load_unaligned32(p, d);
+        return fg32(d, lv);
     }
     uint32_t m = 0;
     int n = im.W - x < 32 ? im.W - x : 32;
@@ -1768,6 +1797,9 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
 //             and the L2 merges the parts (nontemporal partial lines were
 //             1.4x slower).
 //   kStoreAny: plain stores (images wider than kVecMaxW).
+// A batch's images are ordered by store form inside their launch group, so
+// each form's tiles are one range [tbeg, tbeg + ntiles) of the group's tile
+// numbering, labeled by a launch of that form.
 typedef __attribute__((address_space(4))) const int32_t ConstI32;
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer (gfx9 descriptor word 3)
 constexpr uint32_t kDropped = 0x80000000u;  // offset past every buffer this kernel builds (>= its size)
@@ -1775,7 +1807,7 @@ constexpr uint32_t kDropped = 0x80000000u;  // offset past every buffer this ker
 enum StoreForm { kStoreAny = 0, kStore4 = 1, kStore16 = 2 };
 
 template <int NSR, int TW, int BH, int STORE>
-__global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntiles) {
+__global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t tbeg, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
     constexpr int NW = G::NW, TH = G::TH;
@@ -1800,7 +1832,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t ntile
     int32_t pcf[CJ];
     int pn_runs = 0, pn_comp = 0;   // counts of the tile whose tables are in registers
     int qn_runs = 0, qn_comp = 0;   // counts of the tile after it
-    auto tile_of = [&](int slot) { return STORE == kStore4 ? xcd_tile(slot, ntiles) : slot; };
+    auto tile_of = [&](int slot) { return tbeg + (STORE == kStore4 ? xcd_tile(slot, ntiles) : slot); };
     auto counts = [&](int slot) {
         if (slot < ntiles) {
             const int tile = tile_of(slot);

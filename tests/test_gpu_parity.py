@@ -211,6 +211,29 @@ def test_batch_matches_single(ccl):
         assert torch.equal(single, outs[i])
 
 
+def test_batch_mixed_store_forms(ccl):
+    """One launch group whose images need different labeling-pass store
+    forms: rows of W % 4 == 0 into 16-byte aligned labels (16-byte stores),
+    odd widths and a label buffer at a 4-byte offset (4-byte stores), each
+    tile taking its own image's form."""
+    shapes = [(700, 1024), (333, 517), (640, 768), (129, 250), (513, 1283), (256, 512)]
+    imgs = [inputs.bernoulli(H, W, 0.5, seed=40 + i, device=DEV) for i, (H, W) in enumerate(shapes)]
+    outs = [torch.full((H, W), -3, dtype=torch.int32, device=DEV) for H, W in shapes]
+    # the third image's labels at a 4-byte offset inside a larger buffer
+    H2, W2 = shapes[2]
+    big = torch.full((H2 * W2 + 1,), -3, dtype=torch.int32, device=DEV)
+    outs[2] = big[1:].view(H2, W2)
+    assert outs[2].data_ptr() % 16 != 0
+    for conn in (8, 4):
+        say(f"case mixed store forms conn={conn}")
+        ccl.label_batch(imgs, conn=conn, outs=outs)
+        torch.cuda.synchronize()
+        for i, img in enumerate(imgs):
+            ref, _ = oracle.cclremsp(img.cpu().numpy(), conn)
+            assert np.array_equal(outs[i].cpu().numpy(), ref), (conn, i)
+        assert int(big[0].item()) == -3
+
+
 def test_empty_batch_and_single_pixel(ccl):
     assert ccl.label_batch([]) == []
     for v in (0, 1):
