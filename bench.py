@@ -107,26 +107,29 @@ def bench_batched(torch, n, conn, reps, verify):
     single = [torch.empty_like(o) for o in outs]
     px = sum(im.numel() for im in imgs)
     with tempfile.TemporaryDirectory() as td:
-        tile = autotune.Autotuner(os.path.join(td, "tiles.json")).tune_batch(imgs, [conn] * n)
-    log(f"batched conn {conn}: tuned tile {tile}")
-    ccl.reserve(ccl.batch_workspace_bytes([tuple(im.shape) for im in imgs], conn, tile))
+        plan = autotune.Autotuner(os.path.join(td, "tiles.json")).plan_batch(imgs, [conn] * n)
+    tiles = plan["tiles"]
+    log(f"batched conn {conn}: schedule {plan['schedule']} ({plan['ms']})")
+    ccl.reserve(ccl.batch_workspace_bytes([tuple(im.shape) for im in imgs], conn, tiles=tiles))
 
     def loop():
         for im, o in zip(imgs, single):
             ccl.label(im, conn, out=o)
     for _ in range(2):
-        ccl.label_batch(imgs, conn, outs=outs, tile=tile)
+        ccl.label_batch(imgs, conn, outs=outs, tiles=tiles)
         loop()
-    t_batch = _median_ms(torch, lambda: ccl.label_batch(imgs, conn, outs=outs, tile=tile), reps)
+    t_batch = _median_ms(torch, lambda: ccl.label_batch(imgs, conn, outs=outs, tiles=tiles), reps)
     t_loop = _median_ms(torch, loop, reps)
-    g = ccl.BatchGraph(imgs, conn, outs=outs, tile=tile)
+    g = ccl.BatchGraph(imgs, conn, outs=outs, tiles=tiles)
     g.launch()
     t_graph = _median_ms(torch, g.launch, reps)
     g.close()
     torch.cuda.synchronize()
     log(f"batched conn {conn}: timed")
     rec = {
-        "images": n, "conn": conn, "mpx": round(px / 1e6, 2), "tile": list(ccl.tile_shape(tile, conn)),
+        "images": n, "conn": conn, "mpx": round(px / 1e6, 2),
+        "schedule": plan["schedule"], "tuned_ms": plan["ms"],
+        "tile": list(ccl.tile_shape(plan["one_tile"], conn)) if plan["schedule"] == "one tile" else "per bucket",
         "batched_gpx_per_s": round(px / (t_batch * 1e-3) / 1e9, 2),
         "graph_gpx_per_s": round(px / (t_graph * 1e-3) / 1e9, 2),
         "single_loop_gpx_per_s": round(px / (t_loop * 1e-3) / 1e9, 2),

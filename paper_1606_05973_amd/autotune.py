@@ -10,6 +10,13 @@ later calls pick a tile without timing.
 Buckets: log2 of the pixel count rounded to the nearest integer, and the
 aspect class (wide / square / tall).  Batches are tuned as a whole
 (tune_batch): every configuration labels the batch once, the fastest wins.
+
+plan_batch tunes a batch's schedule as well: each size bucket of the batch
+gets the tile that labels that bucket's images fastest, and the whole batch
+is then timed both ways -- one tile for every image (one launch group per
+kind of image) and the per-bucket tiles (one launch group per distinct tile,
+so more launches, each group's latency-bound phases one after another) --
+and the faster assignment is kept.
 """
 from __future__ import annotations
 
@@ -120,6 +127,47 @@ class Autotuner:
                 self.cache[self._key("batch/" + key)] = {"tile": best, "ms": {str(a): round(b, 4) for a, b in res.items()}}
                 self.save()
         return best
+
+    def plan_batch(self, imgs, conns, key: str | None = None, reps: int = 3) -> dict:
+        """Per-image tile ids for labeling this batch as one call, and the
+        schedule they come from: {"tiles": [...], "schedule": "one tile" or
+        "per bucket", "one_tile": id, "ms": {"one tile": t1, "per bucket":
+        t2}, "buckets": {bucket: id}}."""
+        if key is not None:
+            with self._lock:
+                kk = self._key("plan/" + key)
+                if kk in self.cache and len(self.cache[kk]["tiles"]) == len(imgs):
+                    return dict(self.cache[kk])
+        n = len(imgs)
+        conns = list(conns) if isinstance(conns, (list, tuple)) else [conns] * n
+        outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
+        shapes = [tuple(im.shape) for im in imgs]
+        ntiles = len(ccl.tile_configs())
+        ccl.reserve(max(ccl.batch_workspace_bytes(shapes, conns, t) for t in range(1, ntiles + 1)))
+        whole = {t: _time(lambda: ccl.label_batch(imgs, conns, outs=outs, tile=t), reps)
+                 for t in range(1, ntiles + 1)}
+        one = min(whole, key=whole.get)
+        groups = {}
+        for i, (H, W) in enumerate(shapes):
+            groups.setdefault(bucket(H, W, conns[i]), []).append(i)
+        per = {}
+        for b, idx in groups.items():
+            sub, so, sc = [imgs[i] for i in idx], [outs[i] for i in idx], [conns[i] for i in idx]
+            tt = {t: _time(lambda: ccl.label_batch(sub, sc, outs=so, tile=t), reps) for t in range(1, ntiles + 1)}
+            per[b] = min(tt, key=tt.get)
+        tiles = [per[bucket(H, W, conns[i])] for i, (H, W) in enumerate(shapes)]
+        t_per = _time(lambda: ccl.label_batch(imgs, conns, outs=outs, tiles=tiles), reps)
+        plan = {"one_tile": one, "buckets": per,
+                "ms": {"one tile": round(whole[one], 4), "per bucket": round(t_per, 4)}}
+        if t_per < whole[one]:
+            plan.update(tiles=tiles, schedule="per bucket")
+        else:
+            plan.update(tiles=[one] * n, schedule="one tile")
+        if key is not None:
+            with self._lock:
+                self.cache[self._key("plan/" + key)] = plan
+                self.save()
+        return plan
 
 
 _default = None

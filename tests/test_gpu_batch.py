@@ -73,6 +73,24 @@ def test_autotuner_picks_and_caches(ccl, tmp_path):
     torch.cuda.synchronize()
     for img, o in zip(imgs, outs):
         assert np.array_equal(o.cpu().numpy(), _oracle(img, 8)[0])
+    # the schedule tuner: per-bucket tiles or one tile, whichever is faster
+    mix = [inputs.bernoulli(64 + 97 * i, 90 + 211 * (i % 3), 0.5, seed=50 + i, device=DEV) for i in range(7)]
+    conns = [8, 4, 8, 8, 4, 8, 4]
+    say("case autotune plan_batch n=7")
+    plan = t.plan_batch(mix, conns, key="seven")
+    assert plan["schedule"] in ("one tile", "per bucket") and len(plan["tiles"]) == len(mix)
+    assert all(1 <= x <= len(ccl.tile_configs()) for x in plan["tiles"])
+    assert t.plan_batch(mix, conns, key="seven")["tiles"] == plan["tiles"]  # from the cache
+    outs = ccl.label_batch(mix, conns, tiles=plan["tiles"])
+    g = ccl.BatchGraph(mix, conns, tiles=plan["tiles"])
+    try:
+        gout = g.launch()
+        torch.cuda.synchronize()
+        for i, img in enumerate(mix):
+            ref = _oracle(img, conns[i])[0]
+            assert np.array_equal(outs[i].cpu().numpy(), ref) and np.array_equal(gout[i].cpu().numpy(), ref), i
+    finally:
+        g.close()
 
 
 def test_serve_alone_equals_mix(ccl):
