@@ -544,22 +544,23 @@ __device__ __forceinline__ int32_t upper_node(int pc, uint64_t wU, int32_t bU) {
 
 // Node capacity of the tile scan's LDS arrays (a multiple of 32).  The full
 // form holds the most nodes a tile can have (G::RCAP); the compact form holds
-// 9/16 of that, which covers every i.i.d. image: a run of the scanned rows
+// 17/32 of that, which covers every i.i.d. image: a run of the scanned rows
 // starts at a given column with probability q(1 - q) <= 1/4 (q = that the
 // column is occupied), i.e. 1/2 of the capacity on average, with a spread of
 // a few dozen nodes per tile.  A tile with more nodes (stripes,
-// checkerboards) is left to the full form.
+// checkerboards) is left to the full form.  (With 17/32 the compact form of
+// a 64x256 row-pair tile takes 20 KB of LDS: eight tiles share a CU.)
 template <int NSR, int TW, int BH>
-constexpr int compact_cap() { return Geo<NSR, TW, BH>::RCAP / 16 * 9; }
+constexpr int compact_cap() { return Geo<NSR, TW, BH>::RCAP / 32 * 17; }
 
 template <int NSR, int TW, int BH, int CAPN>
 struct ScanLate {
     using G = Geo<NSR, TW, BH>;
     static constexpr int CW = CAPN / 32;
-    uint16_t RT[CAPN];      // component ordinal of each node
-    uint32_t RRB[CW];       // node lies in the block row of its root (bit per node)
-    uint32_t RFB[CW];       // root nodes (bit per node); later boundary components (bit per component)
-    int32_t RFP[CW];
+    uint16_t RT[CAPN];      // root of each node, then its component ordinal
+    uint32_t RFB[CW];       // root nodes (bit per node)
+    uint32_t RBB[CW];       // components touching a shared tile edge (bit per component)
+    int32_t RFP[CW];        // prefix counts of RFB, later of RBB
     uint32_t RK[G::NM];     // keys of interior components (bit per pixel)
     int32_t rowcnt[G::TH];
     int32_t ncomp;          // local component count, for every wave
@@ -573,7 +574,6 @@ struct ScanLds : RunLds<NSR, TW, BH> {
     static constexpr int GN = GRAY ? G::NM : 1;
     static_assert(CAPN % 32 == 0 && CAPN <= G::RCAP, "node capacity");
     int32_t P[CAPN];        // parent array over nodes; later the key of each component
-    uint16_t SP[CAPN];      // start of each node: block row * TW + column
     // gray levels, bit per pixel: same value as the left neighbour (GE), as
     // the pixel above (GV), above-left (GD1), above-right (GD2)
     uint32_t GE[GN], GV[GN], GD1[GN], GD2[GN];
@@ -690,20 +690,6 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
         if (tid == 0)
             im.tcnt[ti * 4 + 0] = kOverflow;
         return;
-    }
-#pragma unroll
-    for (int k = 0; k < (ORD == kCanonical ? UPT : 0); k++) {
-        const int u = tid + k * NT;
-        if (u < G::NU) {
-            const int R = u / NW, w = u % NW;
-            uint32_t bits = t.S[u];
-            int32_t ord = t.base[u];
-            while (bits) {
-                const int bb = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                t.SP[ord++] = (uint16_t)(R * TW + (w << 5) + bb);
-            }
-        }
     }
     // The parent array holds byte offsets (4 x node) until the flatten, so
     // that a union step addresses a parent without a shift.
@@ -921,8 +907,10 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
         for (int r = tid; r < TH; r += NT)
             t.late.rowcnt[r] = 0;
     }
-    for (int i = tid; i < CW; i += NT)
+    for (int i = tid; i < CW; i += NT) {
         t.late.RFB[i] = 0u;
+        t.late.RBB[i] = 0u;
+    }
     __syncthreads();
 
     // 4. flatten; roots are numbered in node order (local components).  A
@@ -949,64 +937,61 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
             t.late.ncomp = tot;
     }
     __syncthreads();
-    const int32_t n_comp = t.late.ncomp;
-    for (int k0 = 0; k0 < n_runs; k0 += NT) {
-        const int k = k0 + tid;
-        bool same_row = false;
-        if (k < n_runs) {
-            const int32_t root = t.P[k] >> 2;
-            t.late.RT[k] = (uint16_t)rank_of(t.late.RFB, t.late.RFP, root);
-            if (ORD == kCanonical)
-                same_row = (t.SP[k] / TW) == (t.SP[root] / TW);
-        }
-        if (ORD == kCanonical) {
-            const uint64_t bal = __ballot(same_row);
-            const int wd = (k0 + wave * 64) >> 5;
-            if (lane == 0 && wd < CW)
-                t.late.RRB[wd] = (uint32_t)bal;
-            if (lane == 32 && wd + 1 < CW)
-                t.late.RRB[wd + 1] = (uint32_t)(bal >> 32);
-        }
-    }
+    // every node notes its root (a node index); the root's rank among the
+    // roots, the node's local component, is taken below per (block row,
+    // word) unit, where the node's block row and first column are known
+    for (int k = tid; k < n_runs; k += NT)
+        t.late.RT[k] = (uint16_t)(t.P[k] >> 2);
     __syncthreads();
+    const int32_t n_comp = t.late.ncomp;
 
-    // 5. canonical key of each component: its first pixel in raster order,
-    // the minimum over its nodes of the node's first pixel (top row first)
+    // 5. canonical key of each component: its first pixel in raster order.
+    // It lies in the block row of the component's root (the root is its
+    // first node in block-row order), so only the nodes of that row offer
+    // their first pixel (top row first); the key is the least of those.
     if (ORD == kCanonical) {
         for (int c = tid; c < n_comp; c += NT)
             t.P[c] = 0x7FFFFFFF;
+        __syncthreads();
     }
-    for (int i = tid; i < CW; i += NT)
-        t.late.RFB[i] = 0u;  // from here on: boundary components
-    __syncthreads();
-    for (int k = tid; k < (ORD == kCanonical ? n_runs : 0); k += NT) {
-        const int sp = t.SP[k];
-        const int R = sp / TW, col = sp % TW;
-        // the first pixel of a component lies in the block row of its root
-        // (the root is its first node in block-row order)
-        if (!((t.late.RRB[k >> 5] >> (k & 31)) & 1u))
-            continue;
-        int32_t key;
-        if (G::RB == 1) {
-            key = sp;
-        } else {
-            const int r0 = R * G::RB;
-            key = (r0 + 1) * TW + col;  // no top pixel: the run's start in the lower row
-            int ww = col >> 5, from = col & 31;
-            for (;;) {
-                const uint32_t tt = t.M[r0 * NW + ww] & mask_ge(from);
-                const uint32_t gap = ~block_mask<NSR, TW, BH>(t.M, R, ww) & mask_ge(from);
-                if (tt && (!gap || __ffs(tt) < __ffs(gap))) {
-                    key = r0 * TW + (ww << 5) + __ffs(tt) - 1;
-                    break;
+    for (int u = tid; u < G::NU; u += NT) {
+        const int R = u / NW, w = u % NW;
+        const int32_t row_first = t.base[R * NW];  // first node of the block row
+        uint32_t bits = t.S[u];
+        int32_t k = t.base[u];
+        while (bits) {
+            const int col = (w << 5) + __ffs(bits) - 1;
+            bits &= bits - 1u;
+            const int32_t root = t.late.RT[k];
+            const int32_t c = rank_of(t.late.RFB, t.late.RFP, root);
+            t.late.RT[k] = (uint16_t)c;
+            // (the root precedes its nodes, so it lies in this block row iff it
+            // is not before the row's first node)
+            if (ORD == kCanonical && root >= row_first) {
+                int32_t key;
+                if (G::RB == 1) {
+                    key = R * TW + col;
+                } else {
+                    const int r0 = R * G::RB;
+                    key = (r0 + 1) * TW + col;  // no top pixel: the run's start in the lower row
+                    int ww = col >> 5, from = col & 31;
+                    for (;;) {
+                        const uint32_t tt = t.M[r0 * NW + ww] & mask_ge(from);
+                        const uint32_t gap = ~block_mask<NSR, TW, BH>(t.M, R, ww) & mask_ge(from);
+                        if (tt && (!gap || __ffs(tt) < __ffs(gap))) {
+                            key = r0 * TW + (ww << 5) + __ffs(tt) - 1;
+                            break;
+                        }
+                        if (gap || ww == NW - 1)
+                            break;
+                        ww++;
+                        from = 0;
+                    }
                 }
-                if (gap || ww == NW - 1)
-                    break;
-                ww++;
-                from = 0;
+                atomicMin(&t.P[c], key);
             }
+            k++;
         }
-        atomicMin(&t.P[t.late.RT[k]], key);
     }
     __syncthreads();
 
@@ -1039,15 +1024,15 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
         }
         if (on) {
             const int32_t comp = t.late.RT[node_at(t, r / G::RB, c)];
-            atomicOr(&t.late.RFB[comp >> 5], 1u << (comp & 31));
+            atomicOr(&t.late.RBB[comp >> 5], 1u << (comp & 31));
         }
     }
     __syncthreads();
     int32_t n_bound = 0;  // known to the first wave, which exports it
     if (wave == 0)
-        n_bound = wave_popcount_prefix(t.late.RFB, t.late.RFP, (n_comp + 31) >> 5, lane);
+        n_bound = wave_popcount_prefix(t.late.RBB, t.late.RFP, (n_comp + 31) >> 5, lane);
     for (int c = tid; c < (ORD == kCanonical ? n_comp : 0); c += NT) {
-        if (!((t.late.RFB[c >> 5] >> (c & 31)) & 1u)) {
+        if (!((t.late.RBB[c >> 5] >> (c & 31)) & 1u)) {
             const int32_t key = t.P[c];
             atomicOr(&t.late.RK[key >> 5], 1u << (key & 31));
             atomicAdd(&t.late.rowcnt[key / TW], 1);
@@ -1058,8 +1043,8 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
     // 7. exports
     const int64_t cbase = (int64_t)ti * G::CAP;
     for (int c = tid; c < n_comp; c += NT) {
-        if ((t.late.RFB[c >> 5] >> (c & 31)) & 1u) {
-            const int32_t j = rank_of(t.late.RFB, t.late.RFP, c);
+        if ((t.late.RBB[c >> 5] >> (c & 31)) & 1u) {
+            const int32_t j = rank_of(t.late.RBB, t.late.RFP, c);
             const uint32_t id = (uint32_t)(cbase + j);
             if (ORD == kCanonical) {
                 const int32_t key = t.P[c];
@@ -1098,7 +1083,7 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
             continue;
         uint16_t v = kNone;
         if ((t.M[r * NW + (c >> 5)] >> (c & 31)) & 1u)
-            v = (uint16_t)rank_of(t.late.RFB, t.late.RFP, t.late.RT[node_at(t, r / G::RB, c)]);
+            v = (uint16_t)rank_of(t.late.RBB, t.late.RFP, t.late.RT[node_at(t, r / G::RB, c)]);
         *dst = v;
     }
     if (ORD == kCanonical) {
@@ -1117,7 +1102,7 @@ __device__ __forceinline__ void scan_tile(const Batch &b, const int tile, ScanLd
         gck[c] = t.P[c];
     uint32_t *gcb = im.cb + (int64_t)ti * G::RW;
     for (int i = tid; i < ((n_comp + 31) >> 5); i += NT)
-        gcb[i] = t.late.RFB[i];
+        gcb[i] = t.late.RBB[i];
     if (tid == 0) {
         im.tcnt[ti * 4 + 0] = n_runs;
         im.tcnt[ti * 4 + 1] = n_comp;
@@ -1146,12 +1131,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
 }
 
 // Compact form: four waves per tile, each lane taking a whole (block row,
-// word) unit, with LDS for compact_cap() nodes, so that six tiles share a
+// word) unit, with LDS for compact_cap() nodes, so that eight tiles share a
 // CU.  Fewer waves per tile issue fewer instructions for the same tile (the
 // per-wave work of each step is paid by half as many waves).
 constexpr int kScanThreadsC = 256;
 template <int NSR, int TW, int BH, int ORD>
-__global__ __launch_bounds__(kScanThreadsC) __attribute__((amdgpu_waves_per_eu(6))) void k_tile_scan_c(Batch b) {
+__global__ __launch_bounds__(kScanThreadsC) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_scan_c(Batch b) {
     constexpr int C = compact_cap<NSR, TW, BH>();
     __shared__ ScanLds<NSR, TW, BH, C> t;
     scan_tile<NSR, TW, BH, ORD, kScanThreadsC, C, true>(b, xcd_tile(blockIdx.x, gridDim.x), t);
