@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 from .build import LIB
@@ -272,31 +273,72 @@ def label_raw(img_ptr: int, H: int, W: int, stride: int, conn: int, labels_ptr: 
     return _lib.ccl_label(img_ptr or None, H, W, stride, conn, labels_ptr or None, _stream_handle(stream))
 
 
+_DESC_FIELDS = ("img", "H", "W", "stride", "conn", "labels", "num_components", "level", "scan", "gray", "order",
+                "tile")
+# numpy view of ccl_image_desc_ex (same offsets and size as the ctypes
+# structure): a batch's descriptors are written column by column
+_DESC_DTYPE = np.dtype({
+    "names": list(_DESC_FIELDS),
+    "formats": [np.uint64, np.int64, np.int64, np.int64, np.int32, np.uint64, np.uint64, np.int32, np.int32,
+                np.int32, np.int32, np.int32],
+    "offsets": [getattr(ImageDescEx, f).offset for f in _DESC_FIELDS],
+    "itemsize": ctypes.sizeof(ImageDescEx)})
+
+
+class _DescArray:
+    """A batch's ccl_image_desc_ex array (numpy-backed); .ptr is what the
+    library calls take, valid while this object lives."""
+
+    def __init__(self, rows: np.ndarray):
+        self.rows = rows
+        self.ptr = rows.ctypes.data_as(ctypes.POINTER(ImageDescEx))
+
+    def __len__(self):
+        return len(self.rows)
+
+
 def _descs(imgs, conns, outs, num_components, levels=None, scans=None, grays=None, orders=None, tiles=None):
     """Extended descriptors of a batch, after checking every buffer the
-    library will write: outs[i] for image i, slot i of num_components."""
+    library will write: outs[i] for image i, slot i of num_components.
+    (One pass with few tensor attribute reads per image, then the fields
+    written column by column; anything unusual goes through the full checks,
+    which raise the detailed errors.)"""
     n = len(imgs)
     if len(outs) != n:
         raise ValueError("one label buffer per image")
-    if n:
-        _check_counts(num_components, n, imgs[0].device)
-    arr = (ImageDescEx * max(n, 1))()
-    for i, img in enumerate(imgs):
-        H, W, stride = _img_geometry(img)
-        _check_out(outs[i], img)
-        if num_components is not None and num_components.device != img.device:
-            raise ValueError("num_components must be on the images' device")
-        arr[i].img = img.data_ptr()
-        arr[i].H, arr[i].W, arr[i].stride = H, W, stride
-        arr[i].conn = int(conns[i])
-        arr[i].labels = outs[i].data_ptr()
-        arr[i].num_components = num_components.data_ptr() + 4 * i if num_components is not None else None
-        arr[i].level = int(levels[i]) if levels is not None else 0
-        arr[i].scan = int(scans[i]) if scans is not None else 0
-        arr[i].gray = int(bool(grays[i])) if grays is not None else 0
-        arr[i].order = int(orders[i]) if orders is not None else 0
-        arr[i].tile = int(tiles[i]) if tiles is not None else 0
-    return arr
+    rows = np.zeros(max(n, 1), dtype=_DESC_DTYPE)
+    if not n:
+        return _DescArray(rows)
+    _check_counts(num_components, n, imgs[0].device)
+    dev = imgs[0].get_device()
+    u8, i32 = torch.uint8, torch.int32
+    ptr, hs, ws, strides, lab = [0] * n, [0] * n, [0] * n, [0] * n, [0] * n
+    for i in range(n):
+        img, out = imgs[i], outs[i]
+        shp = img.shape
+        st = img.stride() if len(shp) == 2 else None
+        if (st is None or img.dtype is not u8 or st[1] != 1 or img.get_device() != dev or dev < 0
+                or not isinstance(out, torch.Tensor) or out.shape != shp or out.dtype is not i32
+                or not out.is_contiguous() or out.get_device() != dev):
+            # the full checks name what is wrong (and accept what they accept)
+            _img_geometry(img)
+            _check_out(out, img)
+            if img.get_device() != dev:
+                raise ValueError("all images of a batch must be on one device")
+        H, W = shp
+        stride = st[0] if H > 1 else W
+        ptr[i], hs[i], ws[i], strides[i], lab[i] = img.data_ptr(), H, W, max(stride, W), out.data_ptr()
+    rows = rows[:n]
+    rows["img"], rows["H"], rows["W"], rows["stride"], rows["labels"] = ptr, hs, ws, strides, lab
+    rows["conn"] = [int(c) for c in conns]
+    if num_components is not None:
+        rows["num_components"] = num_components.data_ptr() + 4 * np.arange(n, dtype=np.uint64)
+    for name, vals in (("level", levels), ("scan", scans), ("order", orders), ("tile", tiles)):
+        if vals is not None:
+            rows[name] = [int(v) for v in vals]
+    if grays is not None:
+        rows["gray"] = [int(bool(v)) for v in grays]
+    return _DescArray(rows)
 
 
 def _per_image(v, n):
@@ -322,7 +364,7 @@ def label_batch(imgs, conn=8, outs=None, tile: int = 0, num_components: torch.Te
     if outs is None:
         outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in imgs]
     arr = _descs(imgs, conns, outs, num_components, levels, scans, grays, orders, tl)
-    _check(_lib.ccl_label_batch_ex(arr, n, int(tile), _stream_handle(stream)))
+    _check(_lib.ccl_label_batch_ex(arr.ptr, n, int(tile), _stream_handle(stream)))
     return outs
 
 
@@ -358,7 +400,7 @@ class BatchGraph:
         self.imgs, self.outs, self.counts = list(imgs), outs, num_components
         arr = _descs(imgs, conns, outs, num_components, levels, scans, grays, orders, tl)
         h = ctypes.c_void_p()
-        _check(_lib.ccl_batch_graph_create(arr, n, int(tile), ctypes.byref(h)))
+        _check(_lib.ccl_batch_graph_create(arr.ptr, n, int(tile), ctypes.byref(h)))
         self._h = h
 
     def launch(self, stream=None):

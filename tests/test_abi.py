@@ -164,6 +164,21 @@ def test_noalloc_checks_on_host():
     assert lib.ccl_workspace_bytes(8192, 8192, 8) > ccl.NOALLOC_SCRATCH_BYTES
 
 
+def test_batch_descriptor_rows_match_the_struct():
+    """The numpy rows a batch call fills have the ccl_image_desc_ex layout."""
+    import numpy as np
+    from paper_1606_05973_amd import ccl
+    dt = ccl._DESC_DTYPE
+    assert dt.itemsize == ctypes.sizeof(ccl.ImageDescEx)
+    for name, ctype in ccl.ImageDescEx._fields_:
+        assert dt.fields[name][1] == getattr(ccl.ImageDescEx, name).offset, name
+        assert dt.fields[name][0].itemsize == ctypes.sizeof(ctype), name
+    rows = np.zeros(2, dtype=dt)
+    rows["H"], rows["tile"], rows["labels"] = [7, 9], [3, 4], [1 << 40, 5]
+    arr = ctypes.cast(rows.ctypes.data, ctypes.POINTER(ccl.ImageDescEx))
+    assert (arr[1].H, arr[1].tile, arr[0].labels, arr[1].labels) == (9, 4, 1 << 40, 5)
+
+
 def test_strerror_and_tiles():
     from paper_1606_05973_amd import ccl
     for code in [0, *ccl.STATUS.values()]:
