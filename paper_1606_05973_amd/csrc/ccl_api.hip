@@ -90,7 +90,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
-    int32_t th, NTY, NTX, NT, nblk, nseg, nedge, nm, rcap, rw, cap, hep, vep;
+    int32_t th, NTY, NTX, NT, nblk, nseg, nedge, nreg, nm, rcap, rw, cap, hep, vep;
     size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
 };
 
@@ -115,6 +115,10 @@ Layout layout_of(const Desc &d, const GroupKey &g) {
     L.nseg = (int32_t)nseg;
     L.nblk = (int32_t)((nseg + kScanChunk - 1) / kScanChunk);
     L.nedge = (int32_t)((L.NTY - 1) * ((W + 31) / 32) + (L.NTX - 1) * ((H + 31) / 32));
+    {
+        const int rx = region_rx(c.tw), ry = region_ry(L.th);
+        L.nreg = ((L.NTY + ry - 1) / ry) * ((L.NTX + rx - 1) / rx);
+    }
     const size_t NT = (size_t)L.NT;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -409,9 +413,10 @@ int persistent_groups(int threads) {
 }
 
 template <int NSR, int TW, int BH, int ORD>
-int launch_all(const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t edges, int64_t blocks, int nimg,
+int launch_all(const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t edges, int64_t regions,
+               int64_t blocks, int nimg,
                hipStream_t s, bool marks) {
-    if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
+    if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX || regions > INT32_MAX)
         return CCL_ERR_TOO_LARGE;
     const dim3 blk(kThreads);
     const dim3 tile_groups((uint32_t)((tiles + kWaves - 1) / kWaves));
@@ -429,9 +434,11 @@ int launch_all(const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t
         hipLaunchKernelGGL((k_tile_scan<NSR, TW, BH, ORD>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, b);
     }
     pm.mark();
-    if (edges > 0)
+    if (edges > 0) {
+        hipLaunchKernelGGL((k_merge_local<NSR, TW, BH, ORD>), dim3((uint32_t)regions), blk, 0, s, b);
         hipLaunchKernelGGL((k_merge<NSR, TW, BH>), dim3((uint32_t)((merge_split(BH) * edges + kThreads - 1) / kThreads)),
                            blk, 0, s, b);
+    }
     pm.mark();
     if (ORD == kCanonical)
         hipLaunchKernelGGL((k_flatten<NSR, TW, BH>), tile_groups, blk, 0, s, b, (int32_t)tiles);
@@ -471,11 +478,11 @@ int launch_all(const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t
 }
 
 int dispatch(const GroupKey &g, const Batch &b, int64_t tiles, const int64_t *form_tiles, int64_t edges,
-             int64_t blocks, int nimg, hipStream_t s, bool marks = true) {
+             int64_t regions, int64_t blocks, int nimg, hipStream_t s, bool marks = true) {
     const TileCfg &c = kTiles[g.tile - 1];
 #define CCL_ORD(N_, W_, B_) \
-    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, form_tiles, edges, blocks, nimg, s, marks) \
-                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, form_tiles, edges, blocks, nimg, s, marks))
+    (g.order == CCL_ORDER_PROVISIONAL ? launch_all<N_, W_, B_, kProvisional>(b, tiles, form_tiles, edges, regions, blocks, nimg, s, marks) \
+                                      : launch_all<N_, W_, B_, kCanonical>(b, tiles, form_tiles, edges, regions, blocks, nimg, s, marks))
 #define CCL_TILE_CASE(N_, W_)                                                                       \
     if (c.nsr == N_ && c.tw == W_)                                                                  \
         return g.kind == kPair ? CCL_ORD(N_, W_, 2) : g.kind == kRow ? CCL_ORD(N_, W_, 1) : CCL_ORD(N_, W_, 0);
@@ -492,14 +499,14 @@ int dispatch(const GroupKey &g, const Batch &b, int64_t tiles, const int64_t *fo
 }
 
 // ------------------------------------------------------------- batches
-// Table of a group of n images: n Img entries, then the n tile0, n edge0
-// and n scan0 keys as a compact array (searched by find_img).
-size_t group_table_bytes(size_t n) { return align_up(n * (sizeof(Img) + 3 * sizeof(int32_t))); }
+// Table of a group of n images: n Img entries, then the n tile0, n edge0,
+// n scan0 and n region0 keys as a compact array (searched by find_img).
+size_t group_table_bytes(size_t n) { return align_up(n * (sizeof(Img) + 4 * sizeof(int32_t))); }
 
 // The most table bytes a batch of n images can need (every image a group of
 // its own at worst).
 size_t max_tables_bytes(size_t n) { return n * group_table_bytes(1); }
-static_assert(sizeof(Img) + 3 * sizeof(int32_t) <= 256, "a group's table takes at most 256 bytes per image");
+static_assert(sizeof(Img) + 4 * sizeof(int32_t) <= 256, "a group's table takes at most 256 bytes per image");
 
 // The layout of a batch's workspace: the tables of its launch groups (in
 // key order), then one region per image.
@@ -545,7 +552,7 @@ size_t batch_bytes(const Desc *descs, int n, int call_tile) { return plan_batch(
 // One group's launch arguments, its table written to `tab_bytes` (host).
 struct GroupRun {
     Batch b;
-    int64_t tiles, edges, blocks;
+    int64_t tiles, edges, regions, blocks;
     int64_t form_tiles[kForms];   // tiles of the 16-byte, 4-byte and plain-store images, in that order
 };
 
@@ -554,7 +561,7 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
     const int n = (int)idx.size();
     Img *tab = reinterpret_cast<Img *>(tab_bytes);
     int32_t *keys = reinterpret_cast<int32_t *>(tab_bytes + (size_t)n * sizeof(Img));
-    int64_t tiles = 0, edges = 0, blocks = 0;
+    int64_t tiles = 0, edges = 0, regions = 0, blocks = 0;
     Batch b{};
     b.n = n;
     int64_t form_tiles[kForms] = {0, 0, 0};
@@ -565,13 +572,16 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
         tab[k].tile0 = (int32_t)tiles;
         tab[k].edge0 = (int32_t)edges;
         tab[k].scan0 = (int32_t)blocks;
+        tab[k].region0 = (int32_t)regions;
         keys[k] = tab[k].tile0;
         keys[n + k] = tab[k].edge0;
         keys[2 * n + k] = tab[k].scan0;
+        keys[3 * n + k] = tab[k].region0;
         tiles += P.lays[i].NT;
         edges += P.lays[i].nedge;
+        regions += P.lays[i].nreg;
         blocks += P.lays[i].nblk;
-        if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX)
+        if (tiles > INT32_MAX || edges > INT32_MAX || blocks > INT32_MAX || regions > INT32_MAX)
             return CCL_ERR_TOO_LARGE;
         form_tiles[form_rank(store_form(d))] += P.lays[i].NT;
     }
@@ -586,6 +596,7 @@ int build_group(const Desc *descs, const Plan &P, size_t g, char *base, char *ta
         out->form_tiles[f] = form_tiles[f];
     out->tiles = tiles;
     out->edges = edges;
+    out->regions = regions;
     out->blocks = blocks;
     return CCL_OK;
 }
@@ -605,7 +616,7 @@ int build_plan(const Desc *descs, const Plan &P, char *base, char *host, std::ve
 int launch_plan(const Plan &P, const std::vector<GroupRun> &runs, hipStream_t stream) {
     for (size_t g = 0; g < P.keys.size(); g++) {
         const int st = dispatch(P.keys[g], runs[g].b, runs[g].tiles, runs[g].form_tiles, runs[g].edges,
-                                runs[g].blocks, (int)P.members[g].size(), stream);
+                                runs[g].regions, runs[g].blocks, (int)P.members[g].size(), stream);
         if (st != CCL_OK)
             return st;
     }
@@ -741,7 +752,7 @@ int ccl_label_noalloc(const uint8_t *img, int64_t H, int64_t W, int64_t stride, 
     b.one = make_img(d, L, base + at);
     int64_t form_tiles[kForms] = {0, 0, 0};
     form_tiles[form_rank(store_form(d))] = L.NT;
-    return dispatch(g, b, L.NT, form_tiles, L.nedge, L.nblk, 1, stream, false);
+    return dispatch(g, b, L.NT, form_tiles, L.nedge, L.nreg, L.nblk, 1, stream, false);
 }
 
 int ccl_label_batch_ex(const ccl_image_desc_ex *descs, int n, int tile, hipStream_t stream) {

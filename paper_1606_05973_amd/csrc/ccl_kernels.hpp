@@ -82,6 +82,7 @@ struct Img {
     int32_t tile0;        // first tile of this image in a batch-wide tile numbering
     int32_t edge0;        // first edge segment (boundary merge kernel)
     int32_t scan0;        // first scan block
+    int32_t region0;      // first region (regional merge kernel)
     int32_t nblk;
     int32_t nseg;         // entries of seg
 };
@@ -99,7 +100,7 @@ struct Batch {
 };
 constexpr int32_t kVecMaxW = 1 << 22;  // keeps a tile's row offsets in bytes below 2^31
 
-enum Key { kTile = 0, kEdge = 1, kScan = 2 };
+enum Key { kTile = 0, kEdge = 1, kScan = 2, kRegion = 3 };
 
 // Image owning global work item `item` (binary search over the start keys).
 // Returned by value: the table is read through the constant address space
@@ -1193,11 +1194,17 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
 // ------------------------------------------------------------------------
 // Foreground bits of positions from..from+31 of an edge line (from % 32 == 0,
 // lines 64-byte aligned): four 16-byte loads; positions at or past n are 0.
+// PARTS > 1: the PARTS adjacent lanes of a segment (lane % PARTS = its
+// part) each load 32 / PARTS of the entries and combine their bits.
+template <int PARTS = 1>
 __device__ __forceinline__ uint32_t line_mask(const uint16_t *line, int from, int n) {
+    static_assert(PARTS == 1 || PARTS == 2 || PARTS == 4, "a part is whole 16-byte loads");
     const u32x4 *q = reinterpret_cast<const u32x4 *>(line + from);
+    const int k0 = PARTS == 1 ? 0 : (int)(threadIdx.x % PARTS) * (4 / PARTS);
     uint32_t m = 0;
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
+    for (int kk = 0; kk < 4 / PARTS; kk++) {
+        const int k = k0 + kk;
         const u32x4 v = q[k];
         const uint32_t d[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -1207,6 +1214,9 @@ __device__ __forceinline__ uint32_t line_mask(const uint16_t *line, int from, in
             m |= (uint32_t)((d[j] >> 16) != kNone) << (bit + 1);
         }
     }
+#pragma unroll
+    for (int x = 1; x < PARTS; x <<= 1)
+        m |= (uint32_t)__shfl_xor((int)m, x, 64);
     const int left = n - from;
     return left >= 32 ? m : (left <= 0 ? 0u : m & ((1u << left) - 1u));
 }
@@ -1246,52 +1256,42 @@ __device__ __forceinline__ void line_bytes(const Img &im, bool horiz, int fixed,
 
 constexpr int merge_split(int bh) { return bh == 2 ? 1 : 2; }
 
-template <int NSR, int TW, int BH>
-__global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
+// The contacts of one 32-pixel segment of a shared tile edge: the segment
+// starts at position `from` of the edge line between tile row (horizontal
+// edge) or tile column (vertical edge) `later_t` and the one before it.  lo
+// and hi are set to the later and the earlier line; cm1 bit c holds a U1
+// contact at position c (partner at c), bit 32 + c a U3 contact (partner at
+// c - 1); cm2 bit c a U2 contact (partner at c + 1).
+template <int NSR, int TW, int BH, int PARTS = 1>
+__device__ __forceinline__ void segment_contacts(const Img &im, bool horiz, int later_t, int from,
+                                                 const uint16_t *&lo, const uint16_t *&hi, uint64_t &cm1,
+                                                 uint32_t &cm2) {
     using G = Geo<NSR, TW, BH>;
     constexpr bool GRAY = G::GRAY;
     constexpr int TH = G::TH;
-    // threads per 32-pixel segment: row-pair runs keep one (their large
-    // components make the split halves repeat each other's unions); single
-    // rows and gray levels split the segment's contacts over two threads,
-    // which halves the longest chains of dependent union steps
-    constexpr int MS = merge_split(BH);
-    const int32_t item2 = blockIdx.x * kThreads + threadIdx.x;
-    const int32_t item = MS == 2 ? item2 >> 1 : item2;
-    const Img &im = find_img(b, item, kEdge);
-    int32_t e = item - im.edge0;
-    const int32_t nxs = (im.W + 31) >> 5, nys = (im.H + 31) >> 5;
-    const int32_t nH = (im.NTY - 1) * nxs, nV = (im.NTX - 1) * nys;
-    if (e < 0 || e >= nH + nV)
-        return;
     const bool conn8 = im.conn == 8;
-    const uint16_t *lo, *hi;   // lo: the line of the later tiles, hi: of the earlier ones
-    int from, n, later_t, period;
-    const bool horiz = e < nH;
+    int n;
+    // cut[c]: a perpendicular tile edge lies between positions c-1 and c.
+    // Segments start at multiples of 32 and tile sides are powers of two:
+    // a side of 32 or more puts at most bit 0 in the mask, a shorter one
+    // (tile heights 4, 8, 16) a bit every TH positions.
+    static_assert((TW & (TW - 1)) == 0 && (TH & (TH - 1)) == 0, "tile sides are powers of two");
+    constexpr uint32_t kRowCuts = TH >= 32 ? 1u : TH == 16 ? 0x00010001u : TH == 8 ? 0x01010101u : 0x11111111u;
+    uint32_t cut, cutn;
     if (horiz) {
-        later_t = 1 + e / nxs;       // tile row of the lower tiles
-        from = (e % nxs) << 5;
         n = im.W;
-        period = TW;
         lo = im.he + ((int64_t)later_t * 2 + 0) * im.hep;
         hi = im.he + ((int64_t)(later_t - 1) * 2 + 1) * im.hep;
+        cut = from % TW == 0 ? 1u : 0u;
+        cutn = (from + 32) % TW == 0 ? 0x80000000u : 0u;
     } else {
-        e -= nH;
-        later_t = 1 + e / nys;       // tile column of the right tiles
-        from = (e % nys) << 5;
         n = im.H;
-        period = TH;
         lo = im.ve + ((int64_t)later_t * 2 + 0) * im.vep;
         hi = im.ve + ((int64_t)(later_t - 1) * 2 + 1) * im.vep;
+        cut = TH >= 32 ? (from % TH == 0 ? 1u : 0u) : kRowCuts;
+        cutn = TH >= 32 ? ((from + 32) % TH == 0 ? 0x80000000u : 0u) : (kRowCuts >> 1) | 0x80000000u;
     }
-    const int earlier_t = later_t - 1;
-    // cut[c]: a perpendicular tile edge lies between positions c-1 and c
-    uint32_t cut = 0u;
-    for (int c = 0; c < 32; c++)
-        if ((from + c) % period == 0)
-            cut |= 1u << c;
-    const uint32_t cutn = (cut >> 1) | (((from + 32) % period == 0) ? 0x80000000u : 0u);
-    const uint32_t m = line_mask(lo, from, n), up = line_mask(hi, from, n);
+    const uint32_t m = line_mask<PARTS>(lo, from, n), up = line_mask<PARTS>(hi, from, n);
     const uint32_t mL = fg_at(lo, from - 1, n) ? 1u : 0u, uL = fg_at(hi, from - 1, n) ? 1u : 0u;
     const uint32_t mR = fg_at(lo, from + 32, n) ? 1u : 0u, uR = fg_at(hi, from + 32, n) ? 1u : 0u;
     const uint32_t mp = ((m << 1) | mL) & ~cut;         // same run continues from c-1
@@ -1305,8 +1305,8 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
         u2 = m & ~mn & un & ~(up & ~cutn);             // earlier run starts at c+1
         u3 = m & ~mp & upp & ~(up & ~cut);             // earlier run ends at c-1
     }
-    uint64_t cm1 = (uint64_t)u1 | ((uint64_t)u3 << 32);  // partner at c (U1) or c-1 (U3)
-    uint32_t cm2 = u2;                                    // partner at c+1 (U2)
+    cm1 = (uint64_t)u1 | ((uint64_t)u3 << 32);  // partner at c (U1) or c-1 (U3)
+    cm2 = u2;                                    // partner at c+1 (U2)
     if (GRAY) {
         // gray levels: object pixels face each other across the edge and
         // connect when their bytes are equal; every such position is a
@@ -1331,16 +1331,25 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
         cm1 = (uint64_t)v | (conn8 ? ((uint64_t)(d1 & (from > 0 ? 0xFFFFFFFFu : 0xFFFFFFFEu)) << 32) : 0ull);
         cm2 = conn8 ? d2 : 0u;
     }
-    if (MS == 2) {
-        const uint32_t hm = (item2 & 1) ? 0xFFFF0000u : 0x0000FFFFu;
-        cm1 &= (uint64_t)hm | ((uint64_t)hm << 32);
-        cm2 &= hm;
-    }
-    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
-    uint64_t *P = im.uf;
-    // flat loop: one union step per iteration, next contact when one ends;
-    // a contact joining the same two components as the previous one is
-    // skipped (long stretches of one component along an edge)
+}
+
+// Rem's union (the step documented above) over the contacts in cm1 / cm2 of
+// the segment starting at `from`, on the packed parent array P at scope S;
+// node_of(pa, pb, rx, ry) gives the nodes of the pixels at positions pa
+// (later line) and pb (earlier line).  A contact joining the same two nodes
+// as the previous one is skipped (long stretches of one component along an
+// edge).  With LASTP the walk of a contact sharing a node with the previous
+// pair starts at the node that union ended on, which lies nearer the root
+// (uniting a set through any of its members is the same union), and a pair
+// whose both ends map to it is done; with row-pair runs on the large
+// components of dense noise that measured slower, so it is off there.
+// Entries pack (key << NB) | node, so that comparing two parents compares
+// their keys.
+template <int S, bool LASTP, int NB, class PT, class NodeOf>
+__device__ __forceinline__ void unite_contacts(PT *P, uint64_t cm1, uint32_t cm2, int from, NodeOf node_of) {
+    using V = decltype(aload<S>(P));
+    constexpr V NODE = NB >= 8 * (int)sizeof(V) ? ~(V)0 : (V)(((V)1 << NB) - 1);
+    // flat loop: one union step per iteration, next contact when one ends
     bool busy = false;
     uint32_t rx = 0, ry = 0, lastx = 0xFFFFFFFFu, lasty = 0xFFFFFFFFu, lastp = 0xFFFFFFFFu;
     for (;;) {
@@ -1358,24 +1367,10 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
                 cm2 &= cm2 - 1u;
                 d = 1;
             }
-            const int pa = from + c, pb = pa + d;
-            if (horiz) {
-                rx = (uint32_t)(((int64_t)later_t * im.NTX + pa / TW) * G::CAP + lo[pa]);
-                ry = (uint32_t)(((int64_t)earlier_t * im.NTX + pb / TW) * G::CAP + hi[pb]);
-            } else {
-                rx = (uint32_t)(((int64_t)(pa / TH) * im.NTX + later_t) * G::CAP + lo[pa]);
-                ry = (uint32_t)(((int64_t)(pb / TH) * im.NTX + earlier_t) * G::CAP + hi[pb]);
-            }
+            node_of(from + c, from + c + d, rx, ry);
             if (rx == lastx && ry == lasty)
                 continue;
-            if constexpr (BH != 2) {
-                // a run of the previous pair is already in one set with
-                // `lastp`, the node that union ended on, which lies nearer the
-                // root: the walk starts there (uniting a set through any of
-                // its members is the same union), and a pair whose both ends
-                // map to it is done.
-                // (Single rows and gray levels only: with row-pair runs on
-                // the large components of dense noise it measured slower.)
+            if constexpr (LASTP) {
                 const uint32_t sx = (rx == lastx || rx == lasty) ? lastp : rx;
                 const uint32_t sy = (ry == lastx || ry == lasty) ? lastp : ry;
                 lastx = rx;
@@ -1390,29 +1385,280 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
             }
             busy = true;
         }
-        const uint64_t px = aload<AG>(P + rx);
-        const uint64_t py = aload<AG>(P + ry);
+        const V px = aload<S>(P + rx);
+        const V py = aload<S>(P + ry);
         if (px == py) {
-            if constexpr (BH != 2)
-                lastp = (uint32_t)px;
+            if constexpr (LASTP)
+                lastp = (uint32_t)(px & NODE);
             busy = false;
             continue;
         }
         const bool xs = px > py;
         const uint32_t n = xs ? rx : ry;
-        const uint64_t pn = xs ? px : py;
-        const uint64_t seen = acas<AG>(P + n, pn, xs ? py : px);
+        const V pn = xs ? px : py;
+        const V seen = acas<S>(P + n, pn, xs ? py : px);
         if (seen == pn) {
-            if ((uint32_t)pn == n) {
-                if constexpr (BH != 2)
-                    lastp = (uint32_t)(xs ? py : px);
+            if ((uint32_t)(pn & NODE) == n) {
+                if constexpr (LASTP)
+                    lastp = (uint32_t)((xs ? py : px) & NODE);
                 busy = false;
                 continue;
             }
-            rx = xs ? (uint32_t)pn : rx;
-            ry = xs ? ry : (uint32_t)pn;
+            rx = xs ? (uint32_t)(pn & NODE) : rx;
+            ry = xs ? ry : (uint32_t)(pn & NODE);
         }
     }
+}
+
+// Keeps part `part` of `parts` equal parts of a segment's positions.
+__device__ __forceinline__ void keep_part(uint64_t &cm1, uint32_t &cm2, int part, int parts) {
+    if (parts > 1) {
+        const int w = 32 / parts;
+        const uint32_t hm = ((1u << w) - 1u) << (part * w);
+        cm1 &= (uint64_t)hm | ((uint64_t)hm << 32);
+        cm2 &= hm;
+    }
+}
+
+// ------------------------------------------------------------------------
+// The boundary merge in two levels.  Tiles are grouped into regions of RY x
+// RX tiles (region_ry / region_rx; RY * TH is a multiple of 32, so that every
+// 32-pixel segment of a vertical edge lies in one region row).  K2a unites
+// the contacts whose two pixels lie in one region on a union-find in LDS, one
+// workgroup per region, and stores the result in the global array: every
+// boundary component whose set has another member gets that set's
+// smallest-key member as its parent (a valid state of the global array:
+// parents only point to smaller keys of the same set).  K2b then unites the
+// remaining contacts, those across region borders (with 8-connectivity also
+// the diagonal ones at a region's corners), with the device-scope Rem steps.
+// Fewer device-scope atomics: with 4 x 2 tiles about 70% of the shared-edge
+// pixels lie inside a region.
+// ------------------------------------------------------------------------
+constexpr int region_rx(int tw) { return tw <= 256 ? 2 : 1; }
+constexpr int region_ry(int th) { return th >= 8 ? 4 : 32 / th; }
+static_assert(region_ry(4) * 4 % 32 == 0 && region_ry(8) * 8 % 32 == 0, "region rows: a multiple of 32");
+constexpr int kRegionSplit = 4;      // threads per segment in K2a
+constexpr int bits_for(int n) { return n <= 1 ? 0 : 1 + bits_for((n + 1) / 2); }   // ceil(log2 n)
+
+template <int NSR, int TW, int BH>
+__host__ __device__ constexpr int region_period(bool horiz) {
+    return horiz ? TW * region_rx(TW) : Geo<NSR, TW, BH>::TH * region_ry(Geo<NSR, TW, BH>::TH);
+}
+
+// rs bit c: a region edge lies between positions from + c - 1 and from + c;
+// re bit c: between from + c and from + c + 1 (period: region size along the
+// line, at least 32, so each mask has at most one bit).
+__device__ __forceinline__ void region_bits(int from, int period, uint32_t &rs, uint32_t &re) {
+    const int m = from % period;
+    const int cs = m == 0 ? 0 : period - m, ce = period - 1 - m;
+    rs = cs < 32 ? 1u << cs : 0u;
+    re = ce < 32 ? 1u << ce : 0u;
+}
+
+// One segment of a region's inner edges (K2a): its line, start, the region
+// tiles of its first later-line and earlier-line pixel, and its contacts.
+struct RegionSeg {
+    const uint16_t *lo, *hi;
+    uint64_t cm1;
+    uint32_t cm2;
+    int from, jl, jh;
+    bool horiz;
+};
+
+// Item `item` of a region (MS items per segment): the horizontal edges
+// between the region's tile rows (each tile column's TW / 32 segments) come
+// first, then the vertical edges between its tile columns (the region's
+// rows, in 32-row segments).  Contacts whose partner lies outside the region
+// are dropped.
+template <int NSR, int TW, int BH, int MS>
+__device__ __forceinline__ RegionSeg region_segment(const Img &im, int item, int ty0, int tx0, int ntx, int nh,
+                                                    int nvs, int row0) {
+    RegionSeg g;
+    int k = item / MS, later_t;
+    const int nhs = nh;
+    if (k < (min(region_ry(Geo<NSR, TW, BH>::TH), im.NTY - ty0) - 1) * nhs) {
+        const int tb = 1 + k / nhs, c = (k % nhs) / (TW / 32);
+        g.horiz = true;
+        later_t = ty0 + tb;
+        g.from = (tx0 * (TW / 32) + k % nhs) << 5;
+        g.jl = tb * ntx + c;
+        g.jh = (tb - 1) * ntx + c;
+    } else {
+        k -= (min(region_ry(Geo<NSR, TW, BH>::TH), im.NTY - ty0) - 1) * nhs;
+        const int cb = 1 + k / nvs;
+        g.horiz = false;
+        later_t = tx0 + cb;
+        g.from = row0 + ((k % nvs) << 5);
+        g.jl = cb;
+        g.jh = cb - 1;
+    }
+    segment_contacts<NSR, TW, BH, BH == 0 ? 1 : MS>(im, g.horiz, later_t, g.from, g.lo, g.hi, g.cm1, g.cm2);
+    uint32_t rs, re;
+    region_bits(g.from, region_period<NSR, TW, BH>(g.horiz), rs, re);
+    g.cm1 &= ~((uint64_t)rs << 32);   // U3 partners left of / above the region
+    g.cm2 &= ~re;                     // U2 partners right of / below it
+    keep_part(g.cm1, g.cm2, item % MS, MS);
+    return g;
+}
+
+// K2a.  Node j * CAP + b of the LDS array is boundary component b of the
+// region's tile j (row-major); its entry packs (key << NB) | parent node,
+// where the key is the component's first pixel as a raster index inside the
+// region (canonical order; the order of the image's raster indices among
+// the region's pixels) or the node itself (provisional order: tiles, then
+// boundary index, as the global ids).
+template <int NSR, int TW, int BH, int ORD>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_merge_local(Batch b) {
+    using G = Geo<NSR, TW, BH>;
+    constexpr int TH = G::TH, CAP = G::CAP, RX = region_rx(TW), RY = region_ry(TH), NTR = RX * RY;
+    constexpr int NN = NTR * CAP, RW = RX * TW;
+    constexpr int NB = bits_for(NN), KB = ORD == kCanonical ? bits_for(RY * TH * RW) : NB;
+    static_assert(NB + KB <= 32, "packed region entries fit 32 bits");
+    constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
+    constexpr int MS = kRegionSplit;
+    __shared__ uint32_t P[NN];
+    __shared__ int32_t nb[NTR];
+    const int tid = threadIdx.x;
+    const Img &im = find_img(b, blockIdx.x, kRegion);
+    const int r = blockIdx.x - im.region0;
+    const int nrx = (im.NTX + RX - 1) / RX;
+    const int ty0 = (r / nrx) * RY, tx0 = (r % nrx) * RX;
+    const int nty = min(RY, im.NTY - ty0), ntx = min(RX, im.NTX - tx0), nt = nty * ntx;
+    const int NTX = im.NTX;
+    const int nxs = (im.W + 31) >> 5;
+    const int hl = min(TW / 32, nxs - (tx0 + ntx - 1) * (TW / 32));   // segments of the last tile column
+    const int nh = (ntx - 1) * (TW / 32) + hl;
+    const int row0 = ty0 * TH, row1 = min((ty0 + nty) * TH, im.H);
+    const int nvs = (row1 + 31) / 32 - row0 / 32;
+    const int items = MS * ((nty - 1) * nh + (ntx - 1) * nvs);
+    // loads: counts, keys (two at a time: CAP is even, so a pair lies in one
+    // tile), the first segment's lines
+    static_assert(CAP % 2 == 0, "key pairs");
+    // region tile j -> (row, column) inside the region (division by RX
+    // at compile time when the region is full width)
+    auto jrow = [&](int j) { return ntx == RX ? j / RX : j; };
+    auto jcol = [&](int j) { return ntx == RX ? j % RX : 0; };
+    if (tid < nt)
+        nb[tid] = im.tcnt[((ty0 + jrow(tid)) * NTX + tx0 + jcol(tid)) * 4 + 2];
+    constexpr int KPT = (NN / 2 + kThreads - 1) / kThreads;
+    uint32_t kv[KPT];
+    const CCL_GLOBAL uint32_t *bkey2 = reinterpret_cast<const CCL_GLOBAL uint32_t *>(im.bkey);
+#pragma unroll
+    for (int i = 0; i < KPT; i++) {
+        const int e = 2 * (tid + i * kThreads), j = e / CAP;
+        kv[i] = 0u;
+        if (ORD == kCanonical && e < nt * CAP)
+            kv[i] = bkey2[((int64_t)((ty0 + jrow(j)) * NTX + tx0 + jcol(j)) * CAP + e % CAP) >> 1];
+    }
+#pragma unroll
+    for (int i = 0; i < KPT; i++) {
+        const int e = 2 * (tid + i * kThreads), j = e / CAP;
+        if (e < NN) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                uint32_t key = (uint32_t)(e + h);
+                if (ORD == kCanonical) {
+                    const int kk = (int)((kv[i] >> (16 * h)) & 0xFFFFu);
+                    key = (uint32_t)((jrow(j) * TH + kk / TW) * RW + jcol(j) * TW + kk % TW);
+                }
+                P[e + h] = (key << NB) | (uint32_t)(e + h);
+            }
+        }
+    }
+    __syncthreads();
+    for (int item = tid; item < items; item += kThreads) {
+        const RegionSeg g = region_segment<NSR, TW, BH, MS>(im, item, ty0, tx0, ntx, nh, nvs, row0);
+        const uint16_t *lo = g.lo, *hi = g.hi;
+        const int jl = g.jl - (g.horiz ? g.from / TW : ty0 * ntx), jh = g.jh - (g.horiz ? g.from / TW : ty0 * ntx);
+        const bool horiz = g.horiz;
+        unite_contacts<WG, BH != 2, NB>(P, g.cm1, g.cm2, g.from, [=](int pa, int pb, uint32_t &rx, uint32_t &ry) {
+            const int da = horiz ? pa / TW : (pa / TH) * ntx, db = horiz ? pb / TW : (pb / TH) * ntx;
+            rx = (uint32_t)((jl + da) * CAP + lo[pa]);
+            ry = (uint32_t)((jh + db) * CAP + hi[pb]);
+        });
+    }
+    __syncthreads();
+    // every node that is not its set's root gets the root (the set's
+    // smallest key) as its global parent
+    constexpr uint32_t NODE = (1u << NB) - 1u;
+    for (int e = tid; e < nt * CAP; e += kThreads) {
+        const int j = e / CAP;
+        if (e % CAP >= nb[j])
+            continue;
+        uint32_t q = (uint32_t)e, pv = P[q];
+        while ((pv & NODE) != q) {
+            q = pv & NODE;
+            pv = P[q];
+        }
+        if (q == (uint32_t)e)
+            continue;
+        const int jq = (int)q / CAP;
+        const uint32_t qid = (uint32_t)(((ty0 + jrow(jq)) * NTX + tx0 + jcol(jq)) * CAP + (int)q % CAP);
+        uint64_t key = qid;
+        if (ORD == kCanonical) {
+            const uint32_t lk = pv >> NB;
+            key = (uint64_t)(row0 + (int)(lk / RW)) * (uint64_t)im.W + (uint64_t)(tx0 * TW + (int)(lk % RW));
+        }
+        im.uf[(int64_t)((ty0 + jrow(j)) * NTX + tx0 + jcol(j)) * CAP + e % CAP] = (key << 32) | qid;
+    }
+}
+
+// K2b: the contacts left by K2a, one item per segment (two per segment for
+// single rows and gray levels).
+template <int NSR, int TW, int BH>
+__global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
+    using G = Geo<NSR, TW, BH>;
+    constexpr int TH = G::TH, RX = region_rx(TW), RY = region_ry(TH);
+    // threads per 32-pixel segment: row-pair runs keep one (their large
+    // components make the split halves repeat each other's unions); single
+    // rows and gray levels split the segment's contacts over two threads,
+    // which halves the longest chains of dependent union steps
+    constexpr int MS = merge_split(BH);
+    const int32_t item2 = blockIdx.x * kThreads + threadIdx.x;
+    const int32_t item = MS == 2 ? item2 >> 1 : item2;
+    const Img &im = find_img(b, item, kEdge);
+    int32_t e = item - im.edge0;
+    const int32_t nxs = (im.W + 31) >> 5, nys = (im.H + 31) >> 5;
+    const int32_t nH = (im.NTY - 1) * nxs, nV = (im.NTX - 1) * nys;
+    if (e < 0 || e >= nH + nV)
+        return;
+    const bool horiz = e < nH;
+    if (!horiz)
+        e -= nH;
+    const int32_t per = horiz ? nxs : nys;
+    const int later_t = 1 + e / per, earlier_t = later_t - 1, from = (e % per) << 5;
+    // on an edge inside a region only the diagonal contacts across the
+    // region's border are left
+    uint64_t keep1 = ~0ull;
+    uint32_t keep2 = ~0u;
+    if (horiz ? later_t % RY != 0 : later_t % RX != 0) {
+        if (im.conn != 8)
+            return;
+        uint32_t rs, re;
+        region_bits(from, region_period<NSR, TW, BH>(horiz), rs, re);
+        if (!(rs | re))
+            return;
+        keep1 = (uint64_t)rs << 32;
+        keep2 = re;
+    }
+    const uint16_t *lo, *hi;
+    uint64_t cm1;
+    uint32_t cm2;
+    segment_contacts<NSR, TW, BH>(im, horiz, later_t, from, lo, hi, cm1, cm2);
+    cm1 &= keep1;
+    cm2 &= keep2;
+    keep_part(cm1, cm2, item2 & (MS - 1), MS);
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+    const int NTX = im.NTX;
+    unite_contacts<AG, BH != 2, 32>(im.uf, cm1, cm2, from, [&](int pa, int pb, uint32_t &rx, uint32_t &ry) {
+        if (horiz) {
+            rx = (uint32_t)(((int64_t)later_t * NTX + pa / TW) * G::CAP + lo[pa]);
+            ry = (uint32_t)(((int64_t)earlier_t * NTX + pb / TW) * G::CAP + hi[pb]);
+        } else {
+            rx = (uint32_t)(((int64_t)(pa / TH) * NTX + later_t) * G::CAP + lo[pa]);
+            ry = (uint32_t)(((int64_t)(pb / TH) * NTX + earlier_t) * G::CAP + hi[pb]);
+        }
+    });
 }
 
 // ------------------------------------------------------------------------
