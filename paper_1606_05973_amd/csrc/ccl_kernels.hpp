@@ -1254,7 +1254,11 @@ __device__ __forceinline__ void line_bytes(const Img &im, bool horiz, int fixed,
     }
 }
 
-constexpr int merge_split(int bh) { return bh == 2 ? 1 : 2; }
+// threads per segment in the boundary merge's global pass (K2b) and in its
+// regional pass (K2a), by run kind: row-pair runs 2 and 4, single rows and
+// gray levels 4 and 8
+constexpr int merge_split(int bh) { return bh == 2 ? 2 : 4; }
+constexpr int region_split(int bh) { return bh == 2 ? 4 : 8; }
 
 // The contacts of one 32-pixel segment of a shared tile edge: the segment
 // starts at position `from` of the edge line between tile row (horizontal
@@ -1437,7 +1441,6 @@ __device__ __forceinline__ void keep_part(uint64_t &cm1, uint32_t &cm2, int part
 constexpr int region_rx(int tw) { return tw <= 256 ? 2 : 1; }
 constexpr int region_ry(int th) { return th >= 8 ? 4 : 32 / th; }
 static_assert(region_ry(4) * 4 % 32 == 0 && region_ry(8) * 8 % 32 == 0, "region rows: a multiple of 32");
-constexpr int kRegionSplit = 4;      // threads per segment in K2a
 constexpr int bits_for(int n) { return n <= 1 ? 0 : 1 + bits_for((n + 1) / 2); }   // ceil(log2 n)
 
 template <int NSR, int TW, int BH>
@@ -1492,7 +1495,7 @@ __device__ __forceinline__ RegionSeg region_segment(const Img &im, int item, int
         g.jl = cb;
         g.jh = cb - 1;
     }
-    segment_contacts<NSR, TW, BH, BH == 0 ? 1 : MS>(im, g.horiz, later_t, g.from, g.lo, g.hi, g.cm1, g.cm2);
+    segment_contacts<NSR, TW, BH, (MS < 4 ? MS : 4)>(im, g.horiz, later_t, g.from, g.lo, g.hi, g.cm1, g.cm2);
     uint32_t rs, re;
     region_bits(g.from, region_period<NSR, TW, BH>(g.horiz), rs, re);
     g.cm1 &= ~((uint64_t)rs << 32);   // U3 partners left of / above the region
@@ -1515,7 +1518,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     constexpr int NB = bits_for(NN), KB = ORD == kCanonical ? bits_for(RY * TH * RW) : NB;
     static_assert(NB + KB <= 32, "packed region entries fit 32 bits");
     constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
-    constexpr int MS = kRegionSplit;
+    constexpr int MS = region_split(BH);
     __shared__ uint32_t P[NN];
     __shared__ int32_t nb[NTR];
     const int tid = threadIdx.x;
@@ -1609,13 +1612,13 @@ template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     using G = Geo<NSR, TW, BH>;
     constexpr int TH = G::TH, RX = region_rx(TW), RY = region_ry(TH);
-    // threads per 32-pixel segment: row-pair runs keep one (their large
-    // components make the split halves repeat each other's unions); single
-    // rows and gray levels split the segment's contacts over two threads,
-    // which halves the longest chains of dependent union steps
+    // MS threads per 32-pixel segment, each taking 32 / MS of its positions:
+    // the longest chains of dependent union steps get MS times shorter (the
+    // contacts at the parts' seams may repeat a union; the edge lines are
+    // loaded once, a part by each thread)
     constexpr int MS = merge_split(BH);
     const int32_t item2 = blockIdx.x * kThreads + threadIdx.x;
-    const int32_t item = MS == 2 ? item2 >> 1 : item2;
+    const int32_t item = item2 / MS;
     const Img &im = find_img(b, item, kEdge);
     int32_t e = item - im.edge0;
     const int32_t nxs = (im.W + 31) >> 5, nys = (im.H + 31) >> 5;
@@ -1644,7 +1647,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     const uint16_t *lo, *hi;
     uint64_t cm1;
     uint32_t cm2;
-    segment_contacts<NSR, TW, BH>(im, horiz, later_t, from, lo, hi, cm1, cm2);
+    segment_contacts<NSR, TW, BH, (MS < 4 ? MS : 4)>(im, horiz, later_t, from, lo, hi, cm1, cm2);
     cm1 &= keep1;
     cm2 &= keep2;
     keep_part(cm1, cm2, item2 & (MS - 1), MS);
