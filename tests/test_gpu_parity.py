@@ -90,6 +90,26 @@ def test_every_tile_shape_adversarial(ccl, name):
             check(ccl, img, conn, tile=tile, what=f"{name} tile sweep")
 
 
+def test_region_corner_diagonals(ccl):
+    """Pixel pairs that touch only diagonally across every point (32 i, 128 j):
+    the corners of the boundary merge's tile regions (whose heights are
+    multiples of 32 rows and widths multiples of 128 columns) lie on that
+    lattice in every tile configuration, so the contacts across region
+    corners, which neither region unites on its own, are all exercised."""
+    H, W = 600, 1100
+    a = np.zeros((H, W), dtype=np.uint8)
+    for y in range(32, H, 32):
+        for x in range(128, W, 128):
+            if (y // 32 + x // 128) % 2:
+                a[y - 1, x - 1] = a[y, x] = 1      # down-right across the corner
+            else:
+                a[y - 1, x] = a[y, x - 1] = 1      # down-left across the corner
+    img = torch.from_numpy(a).to(DEV)
+    for tile in range(1, len(ccl.tile_configs()) + 1):
+        for conn in (8, 4):
+            check(ccl, img, conn, tile=tile, what=f"corner diagonals tile {tile}")
+
+
 @pytest.mark.parametrize("p", [0.3, 0.407, 0.593, 0.7])
 def test_percolation_and_grf(ccl, p):
     img = inputs.bernoulli(1024, 1536, p, seed=11, device=DEV)
