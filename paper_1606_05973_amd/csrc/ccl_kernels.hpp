@@ -1259,6 +1259,7 @@ __device__ __forceinline__ void line_bytes(const Img &im, bool horiz, int fixed,
 // gray levels 4 and 8
 constexpr int merge_split(int bh) { return bh == 2 ? 2 : 4; }
 constexpr int region_split(int bh) { return bh == 2 ? 4 : 8; }
+constexpr int kMergeBatch = 8;   // contacts whose parents K2b loads together (row-pair runs)
 
 // The contacts of one 32-pixel segment of a shared tile edge: the segment
 // starts at position `from` of the edge line between tile row (horizontal
@@ -1412,6 +1413,95 @@ __device__ __forceinline__ void unite_contacts(PT *P, uint64_t cm1, uint32_t cm2
             ry = xs ? ry : (uint32_t)(pn & NODE);
         }
     }
+}
+
+// Takes the next contact of cm1 / cm2 (lowest bit first): position c and
+// partner offset d.  Returns false when there is none.
+__device__ __forceinline__ bool next_contact(uint64_t &cm1, uint32_t &cm2, int &c, int &d) {
+    if (cm1) {
+        const int bit = __ffsll((unsigned long long)cm1) - 1;
+        cm1 &= cm1 - 1;
+        c = bit & 31;
+        d = (bit >> 5) ? -1 : 0;
+        return true;
+    }
+    if (cm2) {
+        c = __ffs(cm2) - 1;
+        cm2 &= cm2 - 1u;
+        d = 1;
+        return true;
+    }
+    return false;
+}
+
+// As unite_contacts, for the device-scope pass: the first MAXC contacts
+// (repeats of the previous node pair skipped) have their two parents loaded
+// together, one round trip for all of them instead of one per union; a
+// contact whose parents are equal is done, and one whose parent pair repeats
+// the previous union's is skipped (its nodes are in those two sets, now one).
+// The others are united from their parents (the same union: parents lie in
+// their children's sets).  Contacts beyond the first MAXC go through
+// unite_contacts.
+template <int S, int NB, int MAXC, class PT, class NodeOf>
+__device__ __forceinline__ void unite_contacts_batched(PT *P, uint64_t cm1, uint32_t cm2, int from, NodeOf node_of) {
+    using V = decltype(aload<S>(P));
+    constexpr V NODE = NB >= 8 * (int)sizeof(V) ? ~(V)0 : (V)(((V)1 << NB) - 1);
+    uint32_t ax[MAXC], ay[MAXC];
+    bool have[MAXC];
+    uint32_t lx = 0xFFFFFFFFu, ly = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < MAXC; i++) {
+        have[i] = false;
+        int c, d;
+        while (next_contact(cm1, cm2, c, d)) {
+            uint32_t rx, ry;
+            node_of(from + c, from + c + d, rx, ry);
+            if (rx == lx && ry == ly)
+                continue;
+            lx = rx;
+            ly = ry;
+            ax[i] = rx;
+            ay[i] = ry;
+            have[i] = true;
+            break;
+        }
+    }
+    V px[MAXC], py[MAXC];
+#pragma unroll
+    for (int i = 0; i < MAXC; i++)
+        if (have[i]) {
+            px[i] = aload<S>(P + ax[i]);
+            py[i] = aload<S>(P + ay[i]);
+        }
+    uint32_t qx = 0xFFFFFFFFu, qy = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < MAXC; i++) {
+        if (!have[i] || px[i] == py[i])
+            continue;
+        uint32_t rx = (uint32_t)(px[i] & NODE), ry = (uint32_t)(py[i] & NODE);
+        if (rx == qx && ry == qy)
+            continue;
+        qx = rx;
+        qy = ry;
+        for (;;) {
+            const V vx = aload<S>(P + rx);
+            const V vy = aload<S>(P + ry);
+            if (vx == vy)
+                break;
+            const bool xs = vx > vy;
+            const uint32_t n = xs ? rx : ry;
+            const V pn = xs ? vx : vy;
+            const V seen = acas<S>(P + n, pn, xs ? vy : vx);
+            if (seen == pn) {
+                if ((uint32_t)(pn & NODE) == n)
+                    break;
+                rx = xs ? (uint32_t)(pn & NODE) : rx;
+                ry = xs ? ry : (uint32_t)(pn & NODE);
+            }
+        }
+    }
+    if (cm1 || cm2)
+        unite_contacts<S, false, NB>(P, cm1, cm2, from, node_of);
 }
 
 // Keeps part `part` of `parts` equal parts of a segment's positions.
@@ -1653,7 +1743,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     keep_part(cm1, cm2, item2 & (MS - 1), MS);
     constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
     const int NTX = im.NTX;
-    unite_contacts<AG, BH != 2, 32>(im.uf, cm1, cm2, from, [&](int pa, int pb, uint32_t &rx, uint32_t &ry) {
+    const auto node_of = [&](int pa, int pb, uint32_t &rx, uint32_t &ry) {
         if (horiz) {
             rx = (uint32_t)(((int64_t)later_t * NTX + pa / TW) * G::CAP + lo[pa]);
             ry = (uint32_t)(((int64_t)earlier_t * NTX + pb / TW) * G::CAP + hi[pb]);
@@ -1661,7 +1751,13 @@ __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
             rx = (uint32_t)(((int64_t)(pa / TH) * NTX + later_t) * G::CAP + lo[pa]);
             ry = (uint32_t)(((int64_t)(pb / TH) * NTX + earlier_t) * G::CAP + hi[pb]);
         }
-    });
+    };
+    // row pairs: parents of a batch of contacts loaded together; single rows
+    // and gray levels: the walk from the last union's node (LASTP)
+    if constexpr (BH == 2)
+        unite_contacts_batched<AG, 32, kMergeBatch>(im.uf, cm1, cm2, from, node_of);
+    else
+        unite_contacts<AG, true, 32>(im.uf, cm1, cm2, from, node_of);
 }
 
 // ------------------------------------------------------------------------
