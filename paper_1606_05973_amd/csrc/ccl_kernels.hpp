@@ -1563,21 +1563,23 @@ struct RegionSeg {
 // first, then the vertical edges between its tile columns (the region's
 // rows, in 32-row segments).  Contacts whose partner lies outside the region
 // are dropped.
+// (The region: tile rows ty0 .. ty0 + nty - 1, columns tx0 .. tx0 + ntx - 1;
+// nh segments along each inner horizontal edge, nvs along each vertical one,
+// its first row row0.)
 template <int NSR, int TW, int BH, int MS>
-__device__ __forceinline__ RegionSeg region_segment(const Img &im, int item, int ty0, int tx0, int ntx, int nh,
-                                                    int nvs, int row0) {
+__device__ __forceinline__ RegionSeg region_segment(const Img &im, int item, int ty0, int tx0, int nty, int ntx,
+                                                    int nh, int nvs, int row0) {
     RegionSeg g;
     int k = item / MS, later_t;
-    const int nhs = nh;
-    if (k < (min(region_ry(Geo<NSR, TW, BH>::TH), im.NTY - ty0) - 1) * nhs) {
-        const int tb = 1 + k / nhs, c = (k % nhs) / (TW / 32);
+    if (k < (nty - 1) * nh) {
+        const int tb = 1 + k / nh, c = (k % nh) / (TW / 32);
         g.horiz = true;
         later_t = ty0 + tb;
-        g.from = (tx0 * (TW / 32) + k % nhs) << 5;
+        g.from = (tx0 * (TW / 32) + k % nh) << 5;
         g.jl = tb * ntx + c;
         g.jh = (tb - 1) * ntx + c;
     } else {
-        k -= (min(region_ry(Geo<NSR, TW, BH>::TH), im.NTY - ty0) - 1) * nhs;
+        k -= (nty - 1) * nh;
         const int cb = 1 + k / nvs;
         g.horiz = false;
         later_t = tx0 + cb;
@@ -1660,7 +1662,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     }
     __syncthreads();
     for (int item = tid; item < items; item += kThreads) {
-        const RegionSeg g = region_segment<NSR, TW, BH, MS>(im, item, ty0, tx0, ntx, nh, nvs, row0);
+        const RegionSeg g = region_segment<NSR, TW, BH, MS>(im, item, ty0, tx0, nty, ntx, nh, nvs, row0);
         const uint16_t *lo = g.lo, *hi = g.hi;
         const int jl = g.jl - (g.horiz ? g.from / TW : ty0 * ntx), jh = g.jh - (g.horiz ? g.from / TW : ty0 * ntx);
         const bool horiz = g.horiz;
