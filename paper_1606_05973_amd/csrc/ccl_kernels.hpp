@@ -80,9 +80,9 @@ struct Img {
     int32_t level;        // foreground iff byte > level (0..255; 0 = nonzero)
     int32_t hep, vep;     // edge line pitches: W and H rounded up to 32 entries (64-byte lines)
     int32_t tile0;        // first tile of this image in a batch-wide tile numbering
-    int32_t edge0;        // first edge segment (boundary merge kernel)
+    int32_t edge0;        // first edge segment (global merge pass, K2b)
     int32_t scan0;        // first scan block
-    int32_t region0;      // first region (regional merge kernel)
+    int32_t region0;      // first region (regional merge pass, K2a)
     int32_t nblk;
     int32_t nseg;         // entries of seg
 };
@@ -1180,9 +1180,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
 
 // ------------------------------------------------------------------------
 // K2: boundary merge (Algorithm 7's boundary loop with Algorithm 8's
-// merger).  One item per 32-pixel segment of every shared tile edge.  The
-// two pixel lines facing each other across the edge are treated as two rows
-// of runs.  Runs are cut where a perpendicular tile edge crosses the line,
+// merger), in two kernels (see the two-level merge below).  The work items
+// are the 32-pixel segments of every shared tile edge.  The two pixel lines
+// facing each other across the edge are treated as two rows of runs.  Runs are cut where a perpendicular tile edge crosses the line,
 // so every run lies in one tile and belongs to one local component; then
 // every pair of runs that touch (8-conn: also diagonally) is united once:
 //   U1 at the first position of their overlap,
