@@ -116,7 +116,7 @@ Layout layout_of(const Desc &d, const GroupKey &g) {
     L.nblk = (int32_t)((nseg + kScanChunk - 1) / kScanChunk);
     L.nedge = (int32_t)((L.NTY - 1) * ((W + 31) / 32) + (L.NTX - 1) * ((H + 31) / 32));
     {
-        const int rx = region_rx(c.tw), ry = region_ry(L.th);
+        const int rx = region_rx(c.tw, gray ? 0 : g.kind == kPair ? 2 : 1), ry = region_ry(L.th);
         L.nreg = ((L.NTY + ry - 1) / ry) * ((L.NTX + rx - 1) / rx);
     }
     const size_t NT = (size_t)L.NT;

@@ -1516,7 +1516,8 @@ __device__ __forceinline__ void keep_part(uint64_t &cm1, uint32_t &cm2, int part
 
 // ------------------------------------------------------------------------
 // The boundary merge in two levels.  Tiles are grouped into regions of RY x
-// RX tiles (region_ry / region_rx; RY * TH is a multiple of 32, so that every
+// RX tiles (region_ry / region_rx: 4 x 2, or 4 x 1 for gray levels and
+// 512-wide tiles; RY * TH is a multiple of 32, so that every
 // 32-pixel segment of a vertical edge lies in one region row).  K2a unites
 // the contacts whose two pixels lie in one region on a union-find in LDS, one
 // workgroup per region, and stores the result in the global array: every
@@ -1528,14 +1529,15 @@ __device__ __forceinline__ void keep_part(uint64_t &cm1, uint32_t &cm2, int part
 // Fewer device-scope atomics: with 4 x 2 tiles about 70% of the shared-edge
 // pixels lie inside a region.
 // ------------------------------------------------------------------------
-constexpr int region_rx(int tw) { return tw <= 256 ? 2 : 1; }
+// (gray levels: one tile column per region measured faster)
+constexpr int region_rx(int tw, int bh) { return bh == 0 || tw > 256 ? 1 : 2; }
 constexpr int region_ry(int th) { return th >= 8 ? 4 : 32 / th; }
 static_assert(region_ry(4) * 4 % 32 == 0 && region_ry(8) * 8 % 32 == 0, "region rows: a multiple of 32");
 constexpr int bits_for(int n) { return n <= 1 ? 0 : 1 + bits_for((n + 1) / 2); }   // ceil(log2 n)
 
 template <int NSR, int TW, int BH>
 __host__ __device__ constexpr int region_period(bool horiz) {
-    return horiz ? TW * region_rx(TW) : Geo<NSR, TW, BH>::TH * region_ry(Geo<NSR, TW, BH>::TH);
+    return horiz ? TW * region_rx(TW, BH) : Geo<NSR, TW, BH>::TH * region_ry(Geo<NSR, TW, BH>::TH);
 }
 
 // rs bit c: a region edge lies between positions from + c - 1 and from + c;
@@ -1605,7 +1607,7 @@ __device__ __forceinline__ RegionSeg region_segment(const Img &im, int item, int
 template <int NSR, int TW, int BH, int ORD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_merge_local(Batch b) {
     using G = Geo<NSR, TW, BH>;
-    constexpr int TH = G::TH, CAP = G::CAP, RX = region_rx(TW), RY = region_ry(TH), NTR = RX * RY;
+    constexpr int TH = G::TH, CAP = G::CAP, RX = region_rx(TW, BH), RY = region_ry(TH), NTR = RX * RY;
     constexpr int NN = NTR * CAP, RW = RX * TW;
     constexpr int NB = bits_for(NN), KB = ORD == kCanonical ? bits_for(RY * TH * RW) : NB;
     static_assert(NB + KB <= 32, "packed region entries fit 32 bits");
@@ -1703,7 +1705,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     using G = Geo<NSR, TW, BH>;
-    constexpr int TH = G::TH, RX = region_rx(TW), RY = region_ry(TH);
+    constexpr int TH = G::TH, RX = region_rx(TW, BH), RY = region_ry(TH);
     // MS threads per 32-pixel segment, each taking 32 / MS of its positions:
     // the longest chains of dependent union steps get MS times shorter (the
     // contacts at the parts' seams may repeat a union; the edge lines are
