@@ -41,7 +41,9 @@ typedef enum {
     CCL_ERR_SHAPE = -2,     /* H <= 0 or W <= 0                                 */
     CCL_ERR_STRIDE = -3,    /* stride < W                                       */
     CCL_ERR_CONN = -4,      /* conn is neither 4 nor 8                          */
-    CCL_ERR_TOO_LARGE = -5, /* H*W >= 2^31 - 1 or a side >= 2^31 - 256 (int32 labels and keys) */
+    CCL_ERR_TOO_LARGE = -5, /* H*W >= 2^31 - 1 or a side >= 2^31 - 256 (int32 labels and keys), or an
+                               image so elongated that tiles x boundary slots per tile reaches 2^31
+                               (32-bit union-find ids; e.g. one row of 2^30 pixels) */
     CCL_ERR_NOMEM = -6,     /* the workspace could not be allocated             */
     CCL_ERR_HIP = -7,       /* a HIP runtime call or kernel launch failed       */
     CCL_ERR_TILE = -8,      /* unknown tile configuration id                    */

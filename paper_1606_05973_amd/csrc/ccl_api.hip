@@ -145,6 +145,11 @@ Layout layout_of(const Desc &d, const GroupKey &g) {
     return L;
 }
 
+// The global union-find addresses the boundary components as tile * CAP +
+// index in 32 bits (and the kernels form that product in int32): images so
+// elongated that their tiles' boundary slots reach 2^31 are refused.
+bool fits_ids(const Layout &L) { return (int64_t)L.NT * L.cap < (int64_t)INT32_MAX; }
+
 int check_image(const void *img, int64_t H, int64_t W, int64_t stride, int conn, const void *labels) {
     if (!img || !labels)
         return CCL_ERR_NULL;
@@ -518,6 +523,7 @@ struct Plan {
     std::vector<size_t> offs;         // region offset of each image
     size_t tables = 0, bytes = 0;
     bool upload = false;              // some group has more than one image (needs its table on the device)
+    bool fits = true;                 // every image's boundary slots fit 32-bit ids (fits_ids)
 };
 
 Plan plan_batch(const Desc *descs, int n, int call_tile) {
@@ -540,6 +546,7 @@ Plan plan_batch(const Desc *descs, int n, int call_tile) {
     P.offs.resize(n);
     for (int i = 0; i < n; i++) {
         P.lays[i] = layout_of(descs[i], key_of(descs[i], call_tile));
+        P.fits &= fits_ids(P.lays[i]);
         P.offs[i] = off;
         off += P.lays[i].bytes;
     }
@@ -679,6 +686,8 @@ int run_plan_in(const Desc *descs, const Plan &P, hipStream_t stream, char *base
 
 int run_batch(const Desc *descs, int n, int call_tile, hipStream_t stream) {
     const Plan P = plan_batch(descs, n, call_tile);
+    if (!P.fits)
+        return CCL_ERR_TOO_LARGE;
     void *ws = nullptr;
     const int st = get_workspace(stream, P.bytes, &ws);
     if (st != CCL_OK)
@@ -740,6 +749,8 @@ int ccl_label_noalloc(const uint8_t *img, int64_t H, int64_t W, int64_t stride, 
     // slot, so that ccl_workspace_bytes states what the call needs
     const GroupKey g = key_of(d, 0);
     const Layout L = layout_of(d, g);
+    if (!fits_ids(L))
+        return CCL_ERR_TOO_LARGE;
     const size_t at = group_table_bytes(1);
     if (at + L.bytes > (size_t)CCL_NOALLOC_SCRATCH_BYTES)
         return CCL_ERR_SCRATCH;
@@ -818,6 +829,8 @@ int ccl_batch_graph_create(const ccl_image_desc_ex *descs, int n, int tile, ccl_
         if ((st = check_desc(descs[i])) != CCL_OK)
             return st;
     const Plan P = plan_batch(descs, n, tile);
+    if (!P.fits)
+        return CCL_ERR_TOO_LARGE;
     ccl_graph *g = new ccl_graph();
     if (hipMalloc(&g->ws, P.bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -969,7 +982,7 @@ const char *ccl_strerror(int status) {
     case CCL_ERR_SHAPE: return "H and W must be positive";
     case CCL_ERR_STRIDE: return "stride must be >= W";
     case CCL_ERR_CONN: return "conn must be 4 or 8";
-    case CCL_ERR_TOO_LARGE: return "H*W must be below 2^31-1";
+    case CCL_ERR_TOO_LARGE: return "image too large: H*W must be below 2^31-1, each side below 2^31-256, and the tiles' boundary slots below 2^31";
     case CCL_ERR_NOMEM: return "workspace allocation failed";
     case CCL_ERR_HIP: return "HIP runtime call or kernel launch failed";
     case CCL_ERR_TILE: return "unknown tile configuration";
@@ -1192,6 +1205,8 @@ int ccl_server_submit(ccl_server *s, const ccl_image_desc_ex *d, hipStream_t rea
     const int st = ccl::check_desc(*d);
     if (st != CCL_OK)
         return st;
+    if (!ccl::fits_ids(ccl::layout_of(*d, ccl::key_of(*d, s->tile))))
+        return CCL_ERR_TOO_LARGE;
     ccl::ServerReq r{};
     r.d = *d;
     r.bytes = s->bytes_of(*d);

@@ -50,6 +50,8 @@ def test_status_codes_on_host():
     # sides that would overflow int32 once rounded up to tiles and edge lines
     assert ccl.label_raw(dummy, 1, (1 << 31) - 200, (1 << 31) - 200, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
     assert ccl.label_raw(dummy, (1 << 31) - 200, 1, 1, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
+    # H*W below 2^31, but 2^22 tiles of one row: more boundary slots than 32-bit ids address
+    assert ccl.label_raw(dummy, 1, 1 << 30, 1 << 30, 8, dummy, stream=0) == S["CCL_ERR_TOO_LARGE"]
     lib = ccl._lib
     assert lib.ccl_label_ex(dummy, 10, 10, 10, 8, dummy, None, 99, None) == S["CCL_ERR_TILE"]
     # the plain batch call (descriptor of seven fields, no options)
