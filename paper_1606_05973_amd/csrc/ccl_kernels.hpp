@@ -38,7 +38,7 @@ constexpr int kThreads = 256;       // threads per workgroup of the small kernel
 constexpr int kWaves = kThreads / 64;  // tiles per workgroup where one wave handles a tile
 constexpr int kTileThreads = 512;   // threads per workgroup of the tile scan and labeling pass (8 wave64)
 constexpr uint16_t kNone = 0xFFFFu;  // background pixel in the edge buffers
-constexpr int kScanChunk = 4096;     // segment counts per scan block (256 x 16)
+constexpr int kScanChunk = 1024;     // segment counts per scan block (256 x 4)
 
 // Per-image description used by every kernel.  img / labels / ncomp belong
 // to the caller, the rest lives in the library workspace.  NT = NTY * NTX
@@ -1931,21 +1931,43 @@ __global__ __launch_bounds__(kThreads) void k_scan_blocks(Batch b) {
     const Img &im = find_img(b, blockIdx.x, kScan);
     const int c = blockIdx.x - im.scan0;
     const int64_t L = im.nseg;
-    const int64_t base = (int64_t)c * kScanChunk + threadIdx.x * 16;
-    int32_t v[16];
-    int32_t sum = 0;
+    static_assert(kScanChunk == 4 * kThreads, "four counts per thread");
+    // four consecutive counts per thread, one 16-byte load where all four
+    // lie in the array (the array starts 256-byte aligned)
+    const int64_t base = (int64_t)c * kScanChunk + threadIdx.x * 4;
+    int32_t v[4];
+    if (base + 3 < L) {
+        const i32x4 q = *reinterpret_cast<const CCL_GLOBAL i32x4 *>(im.seg + base);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
 #pragma unroll
-    for (int i = 0; i < 16; i++) {
-        v[i] = (base + i < L) ? im.seg[base + i] : 0;
-        sum += v[i];
+        for (int i = 0; i < 4; i++)
+            v[i] = (base + i < L) ? im.seg[base + i] : 0;
     }
+    const int32_t sum = v[0] + v[1] + v[2] + v[3];
     int32_t total;
     int32_t run = block_exclusive_scan<kThreads>(sum, &total);
+    int32_t o[4];
 #pragma unroll
-    for (int i = 0; i < 16; i++) {
-        if (base + i < L)
-            im.seg[base + i] = run;
+    for (int i = 0; i < 4; i++) {
+        o[i] = run;
         run += v[i];
+    }
+    if (base + 3 < L) {
+        i32x4 q;
+        q.x = o[0];
+        q.y = o[1];
+        q.z = o[2];
+        q.w = o[3];
+        *reinterpret_cast<CCL_GLOBAL i32x4 *>(im.seg + base) = q;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            if (base + i < L)
+                im.seg[base + i] = o[i];
     }
     if (threadIdx.x == 0)
         im.blk[c] = total;
@@ -1953,14 +1975,22 @@ __global__ __launch_bounds__(kThreads) void k_scan_blocks(Batch b) {
 
 __global__ __launch_bounds__(kThreads) void k_scan_top(Batch b) {
     const Img &im = (b.n == 1) ? b.one : b.tab[blockIdx.x];
+    // four block totals per thread and step
     int32_t carry = 0;
-    for (int base = 0; base < im.nblk; base += kThreads) {
-        int i = base + threadIdx.x;
-        int32_t v = i < im.nblk ? im.blk[i] : 0;
+    for (int base = 0; base < im.nblk; base += 4 * kThreads) {
+        const int i = base + 4 * threadIdx.x;
+        int32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            v[k] = i + k < im.nblk ? im.blk[i + k] : 0;
         int32_t total;
-        int32_t ex = block_exclusive_scan<kThreads>(v, &total);
-        if (i < im.nblk)
-            im.blk[i] = carry + ex;
+        int32_t ex = carry + block_exclusive_scan<kThreads>(v[0] + v[1] + v[2] + v[3], &total);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i + k < im.nblk)
+                im.blk[i + k] = ex;
+            ex += v[k];
+        }
         carry += total;
     }
     if (threadIdx.x == 0 && im.ncomp)
