@@ -2050,14 +2050,16 @@ __global__ __launch_bounds__(kThreads) void k_comp_labels(Batch b, int32_t ntile
     const int64_t cbase = (int64_t)ti * G::CAP;
     // boundary components: label from the scan (roots) or from the root's
     // entries; every root's key goes into RM
+    // (after the flatten a boundary component's entry holds its set's root,
+    // itself for a root: one load tells both)
     auto first = [&](int c, int key) {
         if ((BFB[c >> 5] >> (c & 31)) & 1u) {
             const uint32_t id = (uint32_t)(cbase + rank_of(BFB, BFP, c));
-            if (im.broot[id]) {
+            const uint32_t rid = (uint32_t)im.uf[id];
+            if (rid == id) {
                 gcf[c] = 1 + rowbase[key / TW] + im.bval[id];
                 atomicOr(&RM[key >> 5], 1u << (key & 31));
             } else {
-                const uint32_t rid = (uint32_t)im.uf[id];
                 gcf[c] = 1 + segment_base<NSR, TW, BH>(im, (int)(rid / G::CAP), im.bkey[rid]) + im.bval[rid];
             }
         } else {
