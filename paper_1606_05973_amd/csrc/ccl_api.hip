@@ -91,7 +91,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Workspace layout of one image (byte offsets from the image's base).
 struct Layout {
     int32_t th, NTY, NTX, NT, nblk, nseg, nedge, nreg, nm, rcap, rw, cap, hep, vep;
-    size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, broot, seg, blk, bytes;
+    size_t masks, rt, cb, cf, tcnt, he, ve, uf, bval, bkey, seg, blk, bytes;
 };
 
 Layout layout_of(const Desc &d, const GroupKey &g) {
@@ -138,7 +138,6 @@ Layout layout_of(const Desc &d, const GroupKey &g) {
     L.uf = take(NT * L.cap * sizeof(uint64_t));
     L.bval = take(NT * L.cap * sizeof(int32_t));
     L.bkey = take(NT * L.cap * sizeof(uint16_t));
-    L.broot = take(NT * L.cap * sizeof(uint8_t));
     L.seg = take((size_t)nseg * sizeof(int32_t));
     L.blk = take((size_t)L.nblk * sizeof(int32_t));
     L.bytes = off;
@@ -331,7 +330,6 @@ Img make_img(const Desc &d, const Layout &L, char *base) {
     set_ptr(im.uf, base + L.uf);
     set_ptr(im.bval, base + L.bval);
     set_ptr(im.bkey, base + L.bkey);
-    set_ptr(im.broot, base + L.broot);
     set_ptr(im.seg, base + L.seg);
     set_ptr(im.blk, base + L.blk);
     im.stride = d.stride;

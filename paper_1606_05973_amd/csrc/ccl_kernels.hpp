@@ -70,7 +70,6 @@ struct Img {
     CCL_GLOBAL uint64_t *uf;         // [NT][CAP]   global union-find: (key of parent << 32) | parent id
     CCL_GLOBAL int32_t *bval;        // [NT][CAP]   interior roots before it in its row -> offset -> final label
     CCL_GLOBAL uint16_t *bkey;       // [NT][CAP]   canonical key of boundary component j
-    CCL_GLOBAL uint8_t *broot;       // [NT][CAP]   boundary component j is its set's root
     CCL_GLOBAL int32_t *seg;         // [nseg]      canonical order: roots per (row, tile column) segment,
                                      //             [H][NTX]; provisional order: roots per tile, [NT];
                                      //             then their exclusive scan
@@ -1776,7 +1775,9 @@ template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_flatten(Batch b, int32_t ntiles) {
     using G = Geo<NSR, TW, BH>;
     constexpr int NW = G::NW, TH = G::TH;
+    constexpr int CW = (G::CAP + 31) / 32;
     __shared__ uint32_t RKs[kWaves][G::NM];
+    __shared__ uint32_t RBs[kWaves][CW];   // boundary component j is its set's root (bit)
     __shared__ int32_t rowcs[kWaves][TH];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = blockIdx.x * kWaves + wv;
@@ -1787,12 +1788,14 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b, int32_t ntiles) {
     const int n = im.tcnt[ti * 4 + 2];
     if (n == 0)
         return;
-    uint32_t *RK = RKs[wv];
+    uint32_t *RK = RKs[wv], *RB = RBs[wv];
     int32_t *rowc = rowcs[wv];
     const int ty = ti / im.NTX, tx = ti % im.NTX;
     const int y0 = ty * TH;
     for (int i = lane; i < G::NM; i += 64)
         RK[i] = 0u;
+    for (int i = lane; i < CW; i += 64)
+        RB[i] = 0u;
     for (int r = lane; r < TH; r += 64)
         rowc[r] = 0;
     wave_sync();
@@ -1815,9 +1818,9 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b, int32_t ntiles) {
         const bool is = r == id;
         if (!is)
             im.uf[id] = v;
-        im.broot[id] = is;
         if (is) {
             const int key = im.bkey[id];
+            atomicOr(&RB[j >> 5], 1u << (j & 31));
             atomicOr(&RK[key >> 5], 1u << (key & 31));
             atomicAdd(&rowc[key / TW], 1);
         }
@@ -1827,7 +1830,7 @@ __global__ __launch_bounds__(kThreads) void k_flatten(Batch b, int32_t ntiles) {
     wave_sync();
     for (int j = lane; j < n; j += 64) {
         const uint32_t id = (uint32_t)(cbase + j);
-        if (im.broot[id]) {
+        if ((RB[j >> 5] >> (j & 31)) & 1u) {
             const int key = im.bkey[id];
             im.bval[id] += popc_before(&RK[(key / TW) * NW], key % TW);
         }
