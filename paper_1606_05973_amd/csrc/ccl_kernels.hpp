@@ -2172,6 +2172,11 @@ struct RelabelLds : RunLds<NSR, TW, BH> {
 typedef __attribute__((address_space(4))) const int32_t ConstI32;
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer (gfx9 descriptor word 3)
 constexpr uint32_t kDropped = 0x80000000u;  // offset past every buffer this kernel builds (>= its size)
+// cache policy of the 16-byte label stores: nontemporal (nt) at system
+// coherence scope (sc1); measured ~2% faster than nt alone, cached stores
+// ~8% slower.  (The 4-byte form keeps cached stores: with sc1 its partial
+// lines are no longer merged in the L2, 12% slower on the batch.)
+constexpr int kStoreNtSc1 = 2 | 16;
 
 enum StoreForm { kStoreAny = 0, kStore4 = 1, kStore16 = 2 };
 
@@ -2338,7 +2343,7 @@ __global__ __launch_bounds__(kTileThreads) void k_relabel(Batch b, int32_t tbeg,
                     o.z = (m & 4u) ? t.RF[bs + __popc(s & mask_le(b0 + 2))] : 0;
                     o.w = (m & 8u) ? t.RF[bs + __popc(s & mask_le(b0 + 3))] : 0;
                     const uint32_t off = x0 + c0 < im.W ? (uint32_t)((r * im.W + x0 + c0) * 4) : kDropped;
-                    __builtin_amdgcn_raw_buffer_store_b128(o, rsrc, (int)off, 0, 2 /* nontemporal */);
+                    __builtin_amdgcn_raw_buffer_store_b128(o, rsrc, (int)off, 0, kStoreNtSc1);
                 }
             }
         } else if (STORE == kStore4) {
