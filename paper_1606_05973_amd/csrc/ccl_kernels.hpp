@@ -1699,8 +1699,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     }
 }
 
-// K2b: the contacts left by K2a, one item per segment (two per segment for
-// single rows and gray levels).
+// K2b: the contacts left by K2a, merge_split(BH) items per 32-pixel segment
+// of every shared tile edge (segments wholly inside a region end at once).
 template <int NSR, int TW, int BH>
 __global__ __launch_bounds__(kThreads) void k_merge(Batch b) {
     using G = Geo<NSR, TW, BH>;
